@@ -1,0 +1,318 @@
+"""FP64 CPU oracle for the VEGAS/BASES iteration (arXiv:1010.2107).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It wraps the plain C
+library ``liboracle.so`` built from ``vmc_oracle.c`` (see ``build.py``) and a
+small Python driver for the iteration loop (paper Sec. 3.1, steps 1-6).  It
+shares no code with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+CONST, LINEAR, GAUSS, DGAUSS, GAUSS_AXES, WJETS, PSVOL = range(7)
+
+_lib = None
+
+
+def lib():
+    """Load liboracle.so, building it first if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+
+        _b.build()
+    L = ctypes.CDLL(_LIB_PATH)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    fp = ctypes.POINTER(ctypes.c_float)
+    c_int, c_i64, c_u64, c_u32, c_d = (ctypes.c_int, ctypes.c_int64, ctypes.c_uint64,
+                                       ctypes.c_uint32, ctypes.c_double)
+    L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    L.orc_sample_words.argtypes = [c_u64, c_u32, c_u32, c_u32, c_int, u32p]
+    L.orc_uniform.argtypes = [c_u32]
+    L.orc_uniform.restype = c_d
+    L.orc_bin_batch.argtypes = [c_i64, u32p, i32p, c_int, c_int, i32p, dp]
+    L.orc_map.argtypes = [c_int, c_int, dp, i32p, dp, dp]
+    L.orc_map.restype = c_d
+    L.orc_integrand_nparams.argtypes = [c_int, c_int]
+    L.orc_integrand_ngrad.argtypes = [c_int, c_int]
+    L.orc_integrand.argtypes = [c_int, c_int, dp, dp, c_int, dp]
+    L.orc_integrand.restype = c_d
+    L.orc_rambo_diet.argtypes = [c_int, c_d, dp, dp]
+    L.orc_rambo_diet.restype = c_d
+    L.orc_massless_ps_volume.argtypes = [c_int, c_d]
+    L.orc_massless_ps_volume.restype = c_d
+    L.orc_solve_mass_fraction.argtypes = [c_int, c_int, c_d, dp]
+    L.orc_pass_cuts.argtypes = [c_int, dp, c_d, c_d, c_d, c_d]
+    L.orc_cyclic_sum.argtypes = [c_int, dp]
+    L.orc_cyclic_sum.restype = c_d
+    L.orc_num_cycles.argtypes = [c_int]
+    L.orc_wjets_event.argtypes = [c_int, dp, dp, c_int, dp, dp, dp]
+    L.orc_wjets_event.restype = c_d
+    L.orc_iterate.argtypes = [c_int, c_int, c_int, dp, c_int, dp, c_int, c_i64, c_u64, c_u32,
+                              c_u32, dp, ctypes.c_void_p, dp, fp]
+    L.orc_eval_samples.argtypes = [c_int, c_int, c_int, dp, c_int, dp, c_int, c_i64, c_u64,
+                                   c_u32, c_u32, c_i64, c_i64, u32p, i32p, dp, dp, dp, dp, dp]
+    L.orc_refine.argtypes = [c_int, c_int, dp, dp, c_d, dp]
+    L.orc_combine.argtypes = [c_int, dp, dp, dp, dp, dp]
+    _lib = L
+    return L
+
+
+class IterResult(ctypes.Structure):
+    _fields_ = [("S1", ctypes.c_double), ("S2", ctypes.c_double), ("V", ctypes.c_double),
+                ("I", ctypes.c_double), ("var", ctypes.c_double), ("n_eff", ctypes.c_int64),
+                ("nonfinite", ctypes.c_int64)]
+
+
+def _ptr(a, ctype):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise OracleError(f"{what} failed with code {rc}")
+
+
+# ------------------------------------------------------------------ Philox
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32), _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def sample_words(seed, s, it, kid, d):
+    out = np.zeros(d, dtype=np.uint32)
+    lib().orc_sample_words(seed, s, it, kid, d, _ptr(out, ctypes.c_uint32))
+    return out
+
+
+def uniform(word):
+    return lib().orc_uniform(int(word))
+
+
+def bins_of_words(words, nbins, ng=1, cube_coord=None):
+    w = np.ascontiguousarray(words, dtype=np.uint32).ravel()
+    n = w.size
+    cc = None if cube_coord is None else np.ascontiguousarray(cube_coord, dtype=np.int32).ravel()
+    j = np.zeros(n, dtype=np.int32)
+    delta = np.zeros(n, dtype=np.float64)
+    lib().orc_bin_batch(n, _ptr(w, ctypes.c_uint32), _ptr(cc, ctypes.c_int32), ng, nbins,
+                        _ptr(j, ctypes.c_int32), _ptr(delta, ctypes.c_double))
+    return j, delta
+
+
+def grid_map(edges, j, delta):
+    e = _d(edges)
+    d, n1 = e.shape
+    jj = np.ascontiguousarray(j, dtype=np.int32)
+    dd = _d(delta)
+    x = np.zeros(d)
+    J = lib().orc_map(d, n1 - 1, _ptr(e, ctypes.c_double), _ptr(jj, ctypes.c_int32),
+                      _ptr(dd, ctypes.c_double), _ptr(x, ctypes.c_double))
+    return x, J
+
+
+# -------------------------------------------------------------- integrands
+def nparams(integrand, d):
+    return lib().orc_integrand_nparams(integrand, d)
+
+
+def ngrad(integrand, d):
+    return lib().orc_integrand_ngrad(integrand, d)
+
+
+def integrand(integrand_id, x, theta, want_grad=False):
+    xx = _d(x)
+    th = _d(theta)
+    d = xx.size
+    g = np.zeros(max(ngrad(integrand_id, d), 1)) if want_grad else None
+    f = lib().orc_integrand(integrand_id, d, _ptr(xx, ctypes.c_double), _ptr(th, ctypes.c_double),
+                            th.size, _ptr(g, ctypes.c_double))
+    if want_grad:
+        return f, g[: ngrad(integrand_id, d)]
+    return f
+
+
+def rambo_diet(n, sqrt_shat, r):
+    rr = _d(r)
+    assert rr.size == 3 * n - 4
+    p = np.zeros((n, 4))
+    w = lib().orc_rambo_diet(n, sqrt_shat, _ptr(rr, ctypes.c_double), _ptr(p, ctypes.c_double))
+    return p, w
+
+
+def ps_volume(n, shat):
+    return lib().orc_massless_ps_volume(n, shat)
+
+
+def solve_mass_fraction(n, i, r):
+    t = ctypes.c_double()
+    _check(lib().orc_solve_mass_fraction(n, i, r, ctypes.byref(t)), "solve_mass_fraction")
+    return t.value
+
+
+def pass_cuts(n_p, p, y_boost, ptmin, etamax, drmin):
+    pp = _d(p)
+    return bool(lib().orc_pass_cuts(n_p, _ptr(pp, ctypes.c_double), y_boost, ptmin, etamax, drmin))
+
+
+def cyclic_sum(s):
+    ss = _d(s)
+    return lib().orc_cyclic_sum(ss.shape[0], _ptr(ss, ctypes.c_double))
+
+
+def num_cycles(m):
+    return lib().orc_num_cycles(m)
+
+
+def wjets_event(x, theta, want_grad=False):
+    xx = _d(x)
+    th = _d(theta)
+    d = xx.size
+    n = (d - 4) // 3 + 2
+    p = np.zeros((n, 4))
+    aux = np.zeros(8)
+    g = np.zeros(3) if want_grad else None
+    f = lib().orc_wjets_event(d, _ptr(xx, ctypes.c_double), _ptr(th, ctypes.c_double), th.size,
+                              _ptr(p, ctypes.c_double), _ptr(aux, ctypes.c_double),
+                              _ptr(g, ctypes.c_double))
+    keys = ("x1", "x2", "shat", "Jx", "lum", "Vn", "m2", "pass")
+    out = dict(f=f, p=p, **{k: aux[i] for i, k in enumerate(keys)})
+    if want_grad:
+        out["grad"] = g
+    return out
+
+
+# ------------------------------------------------------------ iteration
+def uniform_edges(d, nbins):
+    return np.tile(np.arange(nbins + 1, dtype=np.float64) / nbins, (d, 1))
+
+
+def iterate(integrand_id, edges, theta, ncall, seed, it, kid=0, ng=1, want_grad=False, w_in=None):
+    """One iteration (steps 2-4): returns dict with S1, S2, V, I, var, n_eff,
+    nonfinite, bins [2][d][N] and (if want_grad) per-parameter gradient sums."""
+    e = _d(edges)
+    d, n1 = e.shape
+    N = n1 - 1
+    th = _d(theta)
+    bins = np.zeros((2, d, N))
+    res = IterResult()
+    P = ngrad(integrand_id, d)
+    g = np.zeros(5 * max(P, 1)) if want_grad else None
+    wi = None if w_in is None else np.ascontiguousarray(w_in, dtype=np.float32)
+    rc = lib().orc_iterate(integrand_id, d, N, _ptr(e, ctypes.c_double), ng, _ptr(th, ctypes.c_double),
+                           th.size, int(ncall), int(seed), int(it), int(kid), _ptr(bins, ctypes.c_double),
+                           ctypes.byref(res), _ptr(g, ctypes.c_double), _ptr(wi, ctypes.c_float))
+    _check(rc, "orc_iterate")
+    out = {f: getattr(res, f) for f, _ in IterResult._fields_}
+    out["bins"] = bins
+    if want_grad:
+        gg = g[: 5 * P].reshape(P, 5) if P else np.zeros((0, 5))
+        out["gsum"] = gg[:, 0].copy()
+        out["gsumsq"] = gg[:, 1].copy()
+        out["gV"] = gg[:, 2].copy()
+        out["grad"] = gg[:, 3].copy()
+        out["grad_var"] = gg[:, 4].copy()
+    return out
+
+
+def eval_samples(integrand_id, edges, theta, ncall, seed, it, s0, count, kid=0, ng=1):
+    e = _d(edges)
+    d, n1 = e.shape
+    th = _d(theta)
+    P = max(ngrad(integrand_id, d), 0)
+    out = dict(words=np.zeros((count, d), np.uint32), j=np.zeros((count, d), np.int32),
+               x=np.zeros((count, d)), jac=np.zeros(count), f=np.zeros(count), w=np.zeros(count),
+               grad=np.zeros((count, max(P, 1))))
+    rc = lib().orc_eval_samples(integrand_id, d, n1 - 1, _ptr(e, ctypes.c_double), ng,
+                                _ptr(th, ctypes.c_double), th.size, int(ncall), int(seed), int(it),
+                                int(kid), int(s0), int(count), _ptr(out["words"], ctypes.c_uint32),
+                                _ptr(out["j"], ctypes.c_int32), _ptr(out["x"], ctypes.c_double),
+                                _ptr(out["jac"], ctypes.c_double), _ptr(out["f"], ctypes.c_double),
+                                _ptr(out["w"], ctypes.c_double), _ptr(out["grad"], ctypes.c_double))
+    _check(rc, "orc_eval_samples")
+    out["grad"] = out["grad"][:, :P]
+    return out
+
+
+def refine(edges, b2, alpha):
+    e = _d(edges)
+    d, n1 = e.shape
+    b = _d(b2)
+    out = np.zeros_like(e)
+    _check(lib().orc_refine(d, n1 - 1, _ptr(e, ctypes.c_double), _ptr(b, ctypes.c_double), alpha,
+                            _ptr(out, ctypes.c_double)), "orc_refine")
+    return out
+
+
+def combine(I, var):
+    Ia = _d(I)
+    va = _d(var)
+    Ib, sb, chi = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib().orc_combine(Ia.size, _ptr(Ia, ctypes.c_double), _ptr(va, ctypes.c_double), ctypes.byref(Ib),
+                      ctypes.byref(sb), ctypes.byref(chi))
+    return Ib.value, sb.value, chi.value
+
+
+# ------------------------------------------------------------ driver
+@dataclass
+class Run:
+    I: list = field(default_factory=list)
+    var: list = field(default_factory=list)
+    Ibar: float = float("nan")
+    sigbar: float = float("nan")
+    chi2dof: float = float("nan")
+    edges: np.ndarray | None = None
+    n_eff: int = 0
+
+
+def integrate(integrand_id, d, nbins, theta, ncall, itmx, seed, alpha=1.5, ng=1, acc=0.0,
+              itmx2=0, edges=None):
+    """VEGAS (itmx2 == 0) or BASES (itmx grid-optimisation iterations, then
+    itmx2 integration iterations with the grid frozen; only the latter are
+    combined).  Paper Sec. 3.1 steps 1-6 and Sec. 6.1 (ITMX, ACC, ITMX1/2)."""
+    e = uniform_edges(d, nbins) if edges is None else _d(edges).copy()
+    run = Run()
+    it = 0
+    phases = [(itmx, True)] + ([(itmx2, False)] if itmx2 else [])
+    for nit, adapt in phases:
+        Is, vs = [], []
+        for _ in range(nit):
+            r = iterate(integrand_id, e, theta, ncall, seed, it, ng=ng)
+            it += 1
+            run.n_eff += r["n_eff"]
+            Is.append(r["I"])
+            vs.append(r["var"])
+            if adapt:
+                e = refine(e, r["bins"][1], alpha)
+            Ib, sb, chi = combine(Is, vs)
+            if acc > 0 and Ib != 0 and sb / abs(Ib) < acc:
+                break
+        run.I, run.var = Is, vs
+        run.Ibar, run.sigbar, run.chi2dof = combine(Is, vs)
+    run.edges = e
+    return run

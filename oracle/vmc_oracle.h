@@ -1,0 +1,140 @@
+/*
+ * vmc_oracle.h -- plain FP64 CPU oracle for the VEGAS/BASES iteration of
+ * Kanzaki, "Monte Carlo integration on GPU" (arXiv:1010.2107).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists so that the tests, the
+ * smoke check and the CPU-baseline leg of the benchmark can check the GPU
+ * library against an independent, slow, obviously-correct implementation.
+ * No product code links, loads or calls it, and it shares no code, header,
+ * table or constant with the GPU library.
+ *
+ * The paper states the method in prose only (Sec. 2 and the six-step
+ * program structure of Sec. 3.1).  The steps are taken from the published
+ * methods it builds on:
+ *   - Philox4x32-10: Salmon, Moraes, Dror, Shaw, "Parallel random numbers:
+ *     as easy as 1, 2, 3", SC'11.
+ *   - VEGAS grid, bin statistic, smoothing, damping, rebinning and the
+ *     combination of iterations: Lepage, J. Comput. Phys. 27 (1978) 192.
+ *   - BASES stratification: Kawabata, Comput. Phys. Commun. 41 (1986) 127.
+ *   - Massless n-body phase space with 3n-4 variables: Plaetzer, "RAMBO on
+ *     diet", arXiv:1308.2922; flat weight as in Kleiss, Stirling, Ellis,
+ *     Comput. Phys. Commun. 40 (1986) 359.
+ *   - Colour-ordered MHV denominators: Parke, Taylor, PRL 56 (1986) 2459.
+ *
+ * Everything is double precision.  All functions are re-entrant except the
+ * lazily built cyclic-order table (built once, guarded by a flag; call
+ * orc_init() from one thread first if that matters).
+ */
+#ifndef VMC_ORACLE_H
+#define VMC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Integrand identifiers (the same numbering is used by the GPU library's
+ * public header; the numbering is an interface, not shared code). */
+enum {
+    ORC_CONST = 0,      /* f = theta[0]                                  */
+    ORC_LINEAR = 1,     /* f = x_0                                       */
+    ORC_GAUSS = 2,      /* prod_a phi(x_a;c,s) / G(c,s)^d, theta=(c,s)   */
+    ORC_DGAUSS = 3,     /* double Gaussian, theta=(c1,c2,s)              */
+    ORC_GAUSS_AXES = 4, /* prod_a phi(x_a;c_a,s)/(s sqrt(pi)), theta=(c_0..c_{d-1},s) */
+    ORC_WJETS = 5,      /* W(->e nu) + n_p partons toy cross section     */
+    ORC_PSVOL = 6       /* PDF x phase-space weight only (no cuts, |M|^2=1) */
+};
+
+/* Error codes returned by the int-valued functions. */
+enum {
+    ORC_OK = 0,
+    ORC_E_INVALID = -1,
+    ORC_E_DIM = -2,
+    ORC_E_NBINS = -3,
+    ORC_E_NCALLS = -4,
+    ORC_E_INTEGRAND = -5,
+    ORC_E_PARAMS = -6,
+    ORC_E_STRAT = -7
+};
+
+/* ---------------------------------------------------------------- Philox */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* The d random words of sample s of iteration `it` of integral `kid`:
+ * word a is word (a mod 4) of the Philox block with counter
+ * (s, a div 4, it, kid) and key (seed lo 32 bits, seed hi 32 bits). */
+void orc_sample_words(uint64_t seed, uint32_t s, uint32_t it, uint32_t kid, int d, uint32_t *out);
+
+/* ------------------------------------------------- uniforms and bin index */
+double orc_uniform(uint32_t word);
+void orc_bin_plain(uint32_t word, int nbins, int *j, double *delta);
+void orc_bin_strat(uint32_t word, int cube_coord, int ng, int nbins, int *j, double *delta);
+/* batch forms for exhaustive tests; ng <= 1 selects the plain form */
+void orc_bin_batch(int64_t n, const uint32_t *words, const int32_t *cube_coord, int ng,
+                   int nbins, int32_t *j, double *delta);
+
+/* ------------------------------------------------------------ grid map */
+/* x_a = e[a][j_a] + delta_a * (e[a][j_a+1]-e[a][j_a]);  returns J = prod N*width */
+double orc_map(int d, int nbins, const double *edges, const int32_t *j, const double *delta, double *x);
+
+/* ----------------------------------------------------------- integrands */
+int orc_integrand_nparams(int id, int d);   /* theta length, <0 on error   */
+int orc_integrand_ngrad(int id, int d);     /* number of differentiable params */
+/* f(x; theta); if grad != NULL also writes df/dtheta_p for p < ngrad. */
+double orc_integrand(int id, int d, const double *x, const double *theta, int ntheta, double *grad);
+
+/* physics pieces, exposed for the tests */
+double orc_rambo_diet(int n, double sqrt_shat, const double *r, double *p /* [n][4] */);
+double orc_massless_ps_volume(int n, double shat);
+int orc_solve_mass_fraction(int n, int i, double r, double *t);
+int orc_pass_cuts(int n_p, const double *p /* [n_p+2][4], CM frame */, double y_boost,
+                  double ptmin, double etamax, double drmin);
+double orc_cyclic_sum(int m, const double *s /* [m][m] symmetric */);
+int orc_num_cycles(int m);
+/* W + n_p partons event: fills momenta p[n][4] (CM frame, order j_1..j_np, e, nu)
+ * and aux = {x1, x2, shat, Jx, lum, Vn, m_enu^2, pass}; returns f (0 when cut). */
+double orc_wjets_event(int d, const double *x, const double *theta, int ntheta,
+                       double *p, double *aux, double *grad);
+
+/* ------------------------------------------------------------ iteration */
+typedef struct {
+    double S1, S2;      /* sum w, sum w^2 over all samples                     */
+    double V;           /* stratified: sum_c (k S2_c - S1_c^2); 0 in plain mode */
+    double I, var;      /* this iteration's estimate and its variance          */
+    int64_t n_eff;      /* samples used                                        */
+    int64_t nonfinite;  /* samples whose w was NaN or Inf                      */
+} orc_iter_result;
+
+/* One iteration of sample -> map -> f -> accumulate.
+ *  edges  [d][nbins+1]; bins out [2][d][nbins] (plane 0: sum w, plane 1: sum w^2)
+ *  ng <= 1 plain mode, else stratified with ng^d cubes, k = ncall div ng^d >= 2.
+ *  gsum (may be NULL) receives per differentiable parameter p the triple
+ *  {sum J df/dp, sum (J df/dp)^2, V_p} followed by {G_p, var G_p} (5 per p).
+ *  w_in (may be NULL): replay mode -- use (double)w_in[s] instead of f*J.
+ */
+int orc_iterate(int id, int d, int nbins, const double *edges, int ng,
+                const double *theta, int ntheta, int64_t ncall, uint64_t seed,
+                uint32_t it, uint32_t kid, double *bins, orc_iter_result *res,
+                double *gsum, const float *w_in);
+
+/* Per-sample dump for samples s0 .. s0+count-1 (stratified when ng > 1).
+ * Any output pointer may be NULL. */
+int orc_eval_samples(int id, int d, int nbins, const double *edges, int ng,
+                     const double *theta, int ntheta, int64_t ncall, uint64_t seed,
+                     uint32_t it, uint32_t kid, int64_t s0, int64_t count,
+                     uint32_t *words, int32_t *j, double *x, double *jac, double *f, double *w,
+                     double *grad /* [count][ngrad] */);
+
+/* Grid refinement of every axis (classic VEGAS), see the .c file. */
+int orc_refine(int d, int nbins, const double *edges_in, const double *b2 /* [d][nbins] */,
+               double alpha, double *edges_out);
+
+/* Weighted combination of m iteration results. */
+void orc_combine(int m, const double *I, const double *var, double *Ibar, double *sigbar,
+                 double *chi2dof);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
