@@ -1,0 +1,171 @@
+"""Benchmark of the VEGAS/BASES hot path on one MI355X.
+
+A step is one iteration of the workload: the sample-and-accumulate pass
+(Philox words -> grid map -> integrand -> FP64 per-bin sums), the estimate
+and running combination, and (in the grid-optimisation phase) the grid
+refinement.  `value` is integrand evaluations per second over the timed
+steps (fail-cut samples count as evaluations, as NCALL does in the paper).
+
+Prints ONE JSON line.  See the design doc for the flop census, the roofline peak
+and how the CPU baseline sample is chosen.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP32 flops per sample of the sample kernel (census of the FP32 arithmetic in
+# the map and the integrand; FP64 accumulation and integer work excluded).
+# map: fma (2) + width*N (1) + Jacobian product (1) per axis; w = f J (1).
+CENSUS = {
+    "gauss": lambda d: 4 * d + 3 * d + 2 + 1,
+    "dgauss": lambda d: 4 * d + 6 * d + 6 + 1,
+    "axes": lambda d: 4 * d + 3 * d + 2 + 1,
+}
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (packed FMA), 256 CU x 2.4 GHz x 256
+PEAK_FP32_NONPACKED = 78.6   # the same without packed FP32 (this build disables packed FP32)
+
+
+def census_for(w):
+    from paper_1010_2107_amd import workloads as W
+    if w.integrand == W.GAUSS:
+        return CENSUS["gauss"](w.dim)
+    if w.integrand == W.DGAUSS:
+        return CENSUS["dgauss"](w.dim)
+    if w.integrand == W.GAUSS_AXES:
+        return CENSUS["axes"](w.dim)
+    from paper_1010_2107_amd import census
+    return census.flops_per_sample(w)
+
+
+def run_loop(grid, w, steps, adjoint=False, fused=False):
+    """Time `steps` iterations; returns (ms_total, kernel_ms, launches)."""
+    import torch
+    grid.reset()
+    grid.stratify(w.ng)
+    th = grid.theta_tensor(w.theta)
+    torch.cuda.synchronize()
+    grid.timing(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for it in range(steps):
+        if fused:
+            grid.fused(w.integrand, th, w.ncall, w.seed, it)
+        else:
+            grid.iterate(w.integrand, th, w.ncall, w.seed, it)
+            if adjoint:
+                grid.adjoint(w.integrand, th, w.ncall, w.seed, it)
+        if it < w.itmx:
+            grid.refine(w.alpha)
+        if w.itmx2 and it + 1 == w.itmx:
+            grid.combine_reset()
+    t1.record()
+    torch.cuda.synchronize()
+    kms, nl = grid.timing(False)
+    return t0.elapsed_time(t1), kms, nl
+
+
+def cpu_baseline(w, edges, budget_s=15.0):
+    """The FP64 oracle, single thread, on a bounded sample of the workload:
+    iterations on the GPU-adapted grid until `budget_s` seconds have passed."""
+    import oracle as O
+    ncall = w.ncall
+    if w.ng <= 1:
+        ncall = min(w.ncall, 2_000_000)
+    n = 0
+    it = 0
+    t0 = time.perf_counter()
+    while True:
+        r = O.iterate(w.integrand, edges, w.theta, ncall, w.seed, 1000 + it, ng=w.ng)
+        n += r["n_eff"]
+        it += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="evals/s", cores=1, kind="oracle",
+                sample=f"{it} oracle iteration(s) x {r['n_eff']} samples of this workload on the GPU-adapted grid "
+                       f"({n} evals, {dt:.1f} s, 1 thread, {platform.processor() or platform.machine()})")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of the "
+              "sample pass is a design note, not a built path", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1010_2107_amd import workloads as W
+    from paper_1010_2107_amd.grid import Grid
+
+    w = W.CONFIGS[args.workload] if args.workload else W.DEFAULT_BENCH
+    steps = args.steps if args.steps is not None else w.itmx + w.itmx2
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    print(f"[bench] workload {w.name} steps {steps} warmup {args.warmup}", file=sys.stderr, flush=True)
+    grid = Grid(w.dim, w.nbins)
+    # warm-up iterations (module load, first launches); not timed
+    if args.warmup:
+        run_loop(grid, w, args.warmup)
+    ms, kms, nl = run_loop(grid, w, steps)
+    res = grid.result()
+    edges = grid.get_edges()
+    n_eff = res["n_eff"]
+    value = n_eff * steps / (ms / 1e3)
+    z = None if w.I_ref is None or res["sigbar"] == 0 else abs(res["Ibar"] - w.I_ref) / res["sigbar"]
+    print(f"[bench] fwd {value:.4g} evals/s, Ibar {res['Ibar']:.6g} +- {res['sigbar']:.3g}", file=sys.stderr,
+          flush=True)
+
+    # forward + adjoint on the same samples (separate adjoint pass, then fused)
+    fa = {}
+    if W.ngrad(w) > 0:
+        ms_a, kms_a, _ = run_loop(grid, w, steps, adjoint=True)
+        ms_f, kms_f, _ = run_loop(grid, w, steps, fused=True)
+        fa = dict(fwd_adj_evals_per_s=n_eff * steps / (ms_a / 1e3), fused_evals_per_s=n_eff * steps / (ms_f / 1e3))
+
+    flops = census_for(w)
+    avg_ms = kms / max(nl, 1)
+    achieved = flops * n_eff / (avg_ms / 1e3) / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+            "frac_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
+            "kernel": "sample-and-accumulate", "avg_launch_ms": avg_ms, "flops_per_sample": flops,
+            "samples_per_launch": n_eff}
+    line = {
+        "metric": "integrand evals/s (fwd)", "value": value, "unit": "evals/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 integrand, f64 sums", "data": "synthetic (counter-based Philox samples)",
+        "config": {"workload": w.name, "dim": w.dim, "nbins": w.nbins, "ncall": w.ncall, "n_eff": n_eff,
+                   "iterations": steps, "mode": "bases-stratified" if w.ng > 1 else "vegas",
+                   "ng": w.ng, "parallelism": "single-gpu"},
+        "result": {"Ibar": res["Ibar"], "sigbar": res["sigbar"], "chi2dof": res["chi2dof"],
+                   "I_ref": w.I_ref, "z": z, "within_3_sigma": None if z is None else bool(z < 3)},
+        "roofline": roof,
+    }
+    line.update(fa)
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(w, edges, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,205 @@
+/*
+ * vmc.h -- C ABI of libvmc.so, an MI355X (gfx950) implementation of the
+ * per-iteration sample-and-accumulate pass and grid refinement of the
+ * VEGAS and BASES adaptive Monte Carlo integrators as parallelised on a
+ * GPU in Kanzaki, "Monte Carlo integration on GPU" (arXiv:1010.2107).
+ *
+ * The paper's user-facing parameters are the dimension (ndim), calls per
+ * iteration (NCALL), iteration count (ITMX) and accuracy (ACC), plus
+ * BASES's grid-optimisation / integration phase split (ITMX1, ITMX2)
+ * (Sec. 6.1 and Appendix A.1.1).  One iteration is steps 2-5 of the
+ * six-step program structure of Sec. 3.1: make points from random numbers,
+ * evaluate the integrand, accumulate, and re-optimise the grid.  In this
+ * library all four run on the GPU; only the driver loop (step 6) is on the
+ * host, and it never needs a device-to-host copy inside the loop.
+ *
+ * Conventions
+ *  - Every call returns 0 (VMC_OK) or a negative VMC_E_* code and never
+ *    throws; vmc_last_error() gives a message for the calling thread.
+ *  - Device memory is owned by the caller and bound to a grid handle with
+ *    vmc_bind(); the library never allocates device memory.  Sizes come
+ *    from vmc_workspace_sizes().
+ *  - `stream` is a hipStream_t (NULL = the null stream).  All device work is
+ *    enqueued on it in call order; no call synchronises the host, except
+ *    vmc_get_edges / vmc_set_edges, which copy synchronously.
+ *  - A handle is not thread-safe: do not use one handle from two host
+ *    threads at once.
+ *  - Integrands are compiled in and chosen by their VMC_* id (the paper's
+ *    gVEGAS likewise compiles the user function into the kernel).
+ */
+#ifndef VMC_H
+#define VMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- errors */
+#define VMC_OK 0
+#define VMC_E_INVALID (-1)   /* bad argument not covered below                */
+#define VMC_E_DIM (-2)       /* dimension outside [1,16] or not compiled in     */
+#define VMC_E_NBINS (-3)     /* bins per axis outside [2,256]                   */
+#define VMC_E_NCALLS (-4)    /* ncall < 2, ncall > 2^32, or < 2 per cube        */
+#define VMC_E_INTEGRAND (-5) /* unknown integrand id                            */
+#define VMC_E_PARAMS (-6)    /* wrong ntheta                                    */
+#define VMC_E_STRAT (-7)     /* ng^dim > 2^40                                   */
+#define VMC_E_GRID (-8)      /* edges not strictly increasing from 0 to 1       */
+#define VMC_E_HIP (-9)       /* a HIP runtime call or launch failed             */
+#define VMC_E_UNBOUND (-10)  /* device buffers not bound with vmc_bind()        */
+#define VMC_E_SCHEDULE (-11) /* schedule values outside their documented range  */
+
+/* --------------------------------------------------------- integrands */
+/* theta is a device array of doubles of the stated length.               */
+#define VMC_CONST 0      /* f = theta[0]; ntheta 1, 1 gradient               */
+#define VMC_LINEAR 1     /* f = x_0; ntheta 0                                */
+#define VMC_GAUSS 2      /* prod_a exp(-(x_a-c)^2/s^2) / G(c,s)^d with        */
+                         /* G = int_0^1 exp(-(x-c)^2/s^2) dx; theta (c, s)    */
+#define VMC_DGAUSS 3     /* [prod_a phi(x_a;c1,s)/G(c1,s) + same with c2]/2; */
+                         /* theta (c1, c2, s)                                 */
+#define VMC_GAUSS_AXES 4 /* prod_a exp(-(x_a-c_a)^2/s^2)/(s sqrt(pi));       */
+                         /* theta (c_0..c_{d-1}, s), d+1 gradients            */
+#define VMC_WJETS 5      /* pp -> W(-> e nu) + n_p partons toy, d = 3 n_p + 4 */
+                         /* (n_p = 1..4); theta (M, Gamma, g, sqrtS, pTmin,   */
+                         /* etamax, dRmin); gradients w.r.t. (M, Gamma, g)    */
+#define VMC_PSVOL 6      /* PDF x massless phase-space weight of VMC_WJETS    */
+                         /* without cuts or |M|^2; theta (sqrtS, pTmin)       */
+
+/* iterate flags */
+#define VMC_FLAG_FP64 1u /* evaluate map and integrand in double precision   */
+                         /* (test instantiation; sums are FP64 either way)    */
+
+/* ------------------------------------------------ scalar block layout */
+/* vmc_bind's `scal` array (VMC_SCAL_LEN doubles) holds, after an        */
+/* iteration has completed on the stream:                                 */
+#define VMC_S_S1 0        /* sum w, w = f J                                   */
+#define VMC_S_S2 1        /* sum w^2                                          */
+#define VMC_S_V 2         /* stratified: sum_c (k S2_c - S1_c^2)              */
+#define VMC_S_NONFINITE 3 /* samples with non-finite w                        */
+#define VMC_S_I 4         /* this iteration's estimate I_k                    */
+#define VMC_S_VAR 5       /* its variance                                     */
+#define VMC_S_NEFF 6      /* samples used this iteration                      */
+#define VMC_S_IBAR 14     /* combined estimate over the iterations folded in  */
+#define VMC_S_SIGBAR 15   /* its standard deviation                           */
+#define VMC_S_CHI2 16     /* chi^2 per degree of freedom (NaN for one)        */
+#define VMC_S_NITER 11    /* number of iterations folded in                   */
+#define VMC_S_GRAD 32     /* adjoint: 5 doubles per gradient p:               */
+                          /* {sum J df/dp, sum (J df/dp)^2, V_p, G_p, var G_p}*/
+#define VMC_SCAL_LEN 128
+#define VMC_MAX_GRAD 17
+
+typedef struct vmc_grid_s *vmc_grid_t;
+
+/* Last error message of the calling thread ("" if none). */
+const char *vmc_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int vmc_version(void);
+
+/* Bytes of the four device buffers a (dim, nbins) grid needs:
+ *   out[0] edges  double[dim][nbins+1]   FP64 bin edges, row per axis
+ *   out[1] table  float [dim][nbins][2]  FP32 (lower edge, width) per bin
+ *   out[2] bins   double[2][dim][nbins]  plane 0: sum w per bin,
+ *                                        plane 1: sum w^2 per bin
+ *   out[3] scal   double[VMC_SCAL_LEN]   scalar block (layout above)
+ * Errors: VMC_E_DIM, VMC_E_NBINS. */
+int vmc_workspace_sizes(int dim, int nbins, size_t out[4]);
+
+/* Create a grid handle for `dim` axes of `nbins` bins each (Sec. 2: each
+ * axis is divided into bins, the volume into hypercubes).  Plain (VEGAS)
+ * sampling until bases_stratify() is called.  Errors: VMC_E_DIM (dim
+ * outside [1,16]), VMC_E_NBINS (outside [2,256]), VMC_E_INVALID (out NULL). */
+int vmc_create(int dim, int nbins, vmc_grid_t *out);
+
+/* Release a handle (not the caller's device buffers). NULL is accepted. */
+int vmc_destroy(vmc_grid_t g);
+
+/* Bind caller-owned device buffers of at least the sizes given by
+ * vmc_workspace_sizes().  They must stay allocated while the handle uses
+ * them.  Errors: VMC_E_INVALID (NULL handle or pointer). */
+int vmc_bind(vmc_grid_t g, double *edges, float *table, double *bins, double *scal);
+
+/* Reset to the uniform grid, clear all accumulators and the running
+ * combination (stream-ordered).  Errors: VMC_E_UNBOUND, VMC_E_HIP. */
+int vmc_reset(vmc_grid_t g, void *stream);
+
+/* BASES-style stratification: split [0,1]^dim into ng^dim equal cubes and
+ * draw k = ncall div ng^dim points in each (the samples of cube c are
+ * s = c + t ng^dim, t < k).  ng <= 1 returns to plain sampling.  Any ng is
+ * accepted (ng need not divide nbins).  Errors: VMC_E_STRAT (ng^dim > 2^40). */
+int bases_stratify(vmc_grid_t g, int ng);
+
+/* One iteration, steps 2-4 of Sec. 3.1 plus the estimate: draw ncall
+ * points with Philox4x32-10 (seed, counter = (sample, word group, it, 0)),
+ * map them through the grid, evaluate the integrand with parameters theta
+ * (device doubles, ntheta of them), accumulate sum w, sum w^2 and the
+ * per-axis per-bin sums (bins buffer), then write I_k and its variance and
+ * fold them into the running combination (weights 1/var).  Stream-ordered.
+ * Errors: VMC_E_UNBOUND, VMC_E_INTEGRAND, VMC_E_PARAMS, VMC_E_NCALLS,
+ * VMC_E_DIM (integrand not compiled for this dim), VMC_E_HIP. */
+int vmc_iterate(vmc_grid_t g, int integrand, const double *theta, int ntheta, int64_t ncall,
+                uint64_t seed, uint32_t it, uint32_t flags, void *stream);
+
+/* Step 5 of Sec. 3.1: re-optimise every axis from the plane-1 bin sums of
+ * the last iteration: 3-point smoothing, normalisation, damping
+ * ((1-rho)/(-ln rho))^alpha, and rebinning to equal damped weight; writes
+ * new FP64 edges and the FP32 table.  An axis whose smoothed sum is zero is
+ * left unchanged; alpha = 0 leaves every axis unchanged.
+ * Errors: VMC_E_INVALID (alpha < 0 or NaN), VMC_E_UNBOUND, VMC_E_HIP. */
+int vmc_refine(vmc_grid_t g, double alpha, void *stream);
+
+/* Clear the running combination (BASES: start of the integration phase). */
+int vmc_combine_reset(vmc_grid_t g, void *stream);
+
+/* Gradient of the integral with respect to the integrand parameters on
+ * the same samples as vmc_iterate with the same (seed, it) and the grid
+ * unchanged since: accumulates sum J df/dtheta_p and its square (and the
+ * per-cube form when stratified), then writes G_p and var G_p into the
+ * scalar block at VMC_S_GRAD.  It does not touch the bin sums, S1/S2/V,
+ * the estimate or the running combination.  Errors: as vmc_iterate, and
+ * VMC_E_INTEGRAND for an integrand without parameters. */
+int vmc_iterate_adjoint(vmc_grid_t g, int integrand, const double *theta, int ntheta, int64_t ncall,
+                        uint64_t seed, uint32_t it, uint32_t flags, void *stream);
+
+/* Forward and adjoint in one pass over the samples: the results of
+ * vmc_iterate (bin sums, estimate, running combination) and of
+ * vmc_iterate_adjoint (gradient block) at the cost of one sample pass.
+ * Errors: as vmc_iterate_adjoint. */
+int vmc_iterate_fused(vmc_grid_t g, int integrand, const double *theta, int ntheta, int64_t ncall,
+                      uint64_t seed, uint32_t it, uint32_t flags, void *stream);
+
+/* Copy the FP64 edges to / from host memory (synchronous on `stream`).
+ * vmc_set_edges validates e[a][0] = 0, e[a][nbins] = 1 and strict increase
+ * (VMC_E_GRID) and rebuilds the FP32 table. */
+int vmc_get_edges(vmc_grid_t g, double *host_edges, void *stream);
+int vmc_set_edges(vmc_grid_t g, const double *host_edges, void *stream);
+
+/* Debug dump of samples s0 .. s0+count-1 of an iteration (same points as
+ * vmc_iterate): words [count][dim] u32, w [count], f [count], jac [count]
+ * (device arrays; w, f, jac as float, or double with VMC_FLAG_FP64; any
+ * may be NULL).  Errors: as vmc_iterate, VMC_E_INVALID for a range beyond
+ * ncall (or k ng^dim when stratified). */
+int vmc_dump_samples(vmc_grid_t g, int integrand, const double *theta, int ntheta, int64_t ncall,
+                     uint64_t seed, uint32_t it, uint32_t flags, int64_t s0, int64_t count,
+                     uint32_t *words, void *w, void *f, void *jac, void *stream);
+
+/* Launch shape of the sample kernels.  block_samples: samples (plain) or
+ * cube units (stratified) per thread block, a multiple of 256 in
+ * [256, 2^24], or 0 for the built-in choice; chunks_per_cube: lanes that
+ * share one cube in stratified mode, a power of two in [1, 64], or 0 for
+ * the built-in choice.  Errors: VMC_E_SCHEDULE. */
+int vmc_set_schedule(vmc_grid_t g, int block_samples, int chunks_per_cube);
+
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * sample-kernel launch of this handle while enabled.  Each call waits for
+ * the recorded launches, returns their summed duration (ms) and count
+ * (either pointer may be NULL), forgets them, and then enables (enable != 0)
+ * or disables recording.  Errors: VMC_E_INVALID, VMC_E_HIP. */
+int vmc_timing(vmc_grid_t g, int enable, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,22 @@
+"""MI355X (gfx950) VEGAS/BASES hot path of Kanzaki, "Monte Carlo integration
+on GPU" (arXiv:1010.2107): HIP kernels behind the C ABI in include/vmc.h,
+with this thin Python binding (ctypes + torch device memory and streams).
+
+The HIP library is loaded on first use; if it is missing or cannot be
+loaded every call raises VmcNotBuilt -- there is no CPU fallback.
+"""
+from ._lib import (CONST, DGAUSS, FLAG_FP64, GAUSS, GAUSS_AXES, LINEAR, PSVOL, WJETS, VmcError, VmcNotBuilt,
+                   header_functions, lib)
+
+__all__ = ["CONST", "LINEAR", "GAUSS", "DGAUSS", "GAUSS_AXES", "WJETS", "PSVOL", "FLAG_FP64", "VmcError",
+           "VmcNotBuilt", "lib", "header_functions", "Grid", "integrate"]
+
+
+def __getattr__(name):
+    if name == "Grid":
+        from .grid import Grid
+        return Grid
+    if name == "integrate":
+        from .driver import integrate
+        return integrate
+    raise AttributeError(name)

@@ -1,0 +1,160 @@
+// vmc_device.hpp -- device primitives of the sample-and-accumulate pass
+// (steps 2-4 of the six-step structure of Kanzaki, arXiv:1010.2107,
+// Sec. 3.1) for gfx950: counter-based random words, exact bin index,
+// LDS-resident grid table, and block reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vmc {
+
+constexpr int kBlock = 256;  // 4 wave64 per block
+constexpr int kWave = 64;
+constexpr int kMaxGrad = 17;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// products and xors; the key advances by the Weyl increments between
+// rounds.  The key words are kernel arguments, so the key schedule lives in
+// scalar registers; the products map onto v_mad_u64_u32.
+// ---------------------------------------------------------------------------
+struct Key {
+  uint32_t k0, k1;
+};
+
+__device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, Key key,
+                                         uint32_t (&out)[4]) {
+  uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
+    const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+    const uint32_t x0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ k0;
+    const uint32_t x2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ k1;
+    c1 = static_cast<uint32_t>(pb);
+    c3 = static_cast<uint32_t>(pa);
+    c0 = x0;
+    c2 = x2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// The D words of sample s: word a is word a%4 of the block with counter
+// (s, a/4, it, kid).
+template <int D>
+__device__ __forceinline__ void sample_words(uint32_t s, uint32_t it, uint32_t kid, Key key,
+                                             uint32_t (&w)[D]) {
+#pragma unroll
+  for (int g = 0; g < (D + 3) / 4; ++g) {
+    uint32_t blk[4];
+    philox10(s, static_cast<uint32_t>(g), it, kid, key, blk);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (4 * g + q < D) w[4 * g + q] = blk[q];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Bin index.  The uniform is u = (2m+1) 2^-24 with m the top 23 bits of the
+// word.  With y N = (2m+1) N 2^-24 the bin is its integer part and the
+// in-bin offset its fraction, both exact in 32-bit integer arithmetic for
+// N <= 256.  Stratified: y = (c + u)/ng, so y N = (c 2^24 + 2m+1) N /
+// (ng 2^24); when ng divides N this is c (N/ng) + (2m+1)(N/ng) 2^-24.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void bin_plain(uint32_t word, uint32_t nbins, int& j, T& delta) {
+  const uint32_t P = ((word >> 9) * 2u + 1u) * nbins;
+  j = static_cast<int>(P >> 24);
+  delta = static_cast<T>(static_cast<int>(P & 0xFFFFFFu)) * static_cast<T>(5.9604644775390625e-08);
+}
+
+template <typename T>
+__device__ __forceinline__ void bin_strat_div(uint32_t word, uint32_t ca, uint32_t per_cube, int& j,
+                                              T& delta) {
+  // ng divides nbins; per_cube = nbins / ng
+  const uint32_t P = ((word >> 9) * 2u + 1u) * per_cube;
+  j = static_cast<int>(ca * per_cube + (P >> 24));
+  delta = static_cast<T>(static_cast<int>(P & 0xFFFFFFu)) * static_cast<T>(5.9604644775390625e-08);
+}
+
+template <typename T>
+__device__ __forceinline__ void bin_strat_gen(uint32_t word, uint32_t ca, uint32_t ng, uint32_t nbins,
+                                              int& j, T& delta) {
+  const uint64_t Q = ((static_cast<uint64_t>(ca) << 24) + ((word >> 9) * 2u + 1u)) * nbins;
+  const uint64_t Dn = static_cast<uint64_t>(ng) << 24;
+  const uint64_t q = Q / Dn;
+  j = static_cast<int>(q);
+  delta = static_cast<T>(static_cast<double>(Q - q * Dn) / static_cast<double>(Dn));
+}
+
+// Grid table entry: lower edge and width of a bin.
+template <typename T>
+struct TabEntry;
+template <>
+struct TabEntry<float> {
+  using type = float2;
+};
+template <>
+struct TabEntry<double> {
+  using type = double2;
+};
+
+// ---------------------------------------------------------------------------
+// math overloads
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float vexp(float x) { return expf(x); }
+__device__ __forceinline__ double vexp(double x) { return exp(x); }
+__device__ __forceinline__ float vlog(float x) { return logf(x); }
+__device__ __forceinline__ double vlog(double x) { return log(x); }
+__device__ __forceinline__ float vsqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double vsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ bool vfinite(float x) { return isfinite(x); }
+__device__ __forceinline__ bool vfinite(double x) { return isfinite(x); }
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void global_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+// Sum NV per-thread values over the block and add the totals to dst[idx[i]]
+// with one global atomic each.  `red` is LDS scratch of 4*NV doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum_to_global(const double (&v)[NV], double* red, double* dst,
+                                                    const int (&idx)[NV]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double t = wave_sum(v[i]);
+    if (lane == 0) red[wave * NV + i] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kBlock / kWave; ++w) t += red[w * NV + i];
+      if (t != 0.0) global_add(dst + idx[i], t);
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace vmc

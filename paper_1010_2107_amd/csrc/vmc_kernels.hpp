@@ -1,0 +1,408 @@
+// vmc_kernels.hpp -- the sample-and-accumulate kernels (steps 2-4 of the
+// six-step structure of Kanzaki, arXiv:1010.2107, Sec. 3.1).
+//
+// One sample per lane per loop trip: Philox words -> bin index -> grid map
+// from the LDS table -> integrand -> w = f J.  Each block keeps a private
+// FP64 histogram of sum w and sum w^2 per axis and bin in LDS (2 D LDS
+// atomics per sample) and merges it with one global FP64 atomic per
+// non-zero bin when it finishes; scalar sums are reduced over the wave with
+// DPP shuffles and over the block through LDS, then added with one atomic
+// per block.  Samples are never stored: the random stream is counter-based,
+// so any pass can regenerate any sample.
+#pragma once
+
+#include "vmc_device.hpp"
+
+namespace vmc {
+
+// Scalar block layout (doubles); mirrored in the public header.
+enum : int {
+  S_S1 = 0,
+  S_S2 = 1,
+  S_V = 2,
+  S_NONFIN = 3,
+  S_I = 4,
+  S_VAR = 5,
+  S_NEFF = 6,
+  S_W = 8,
+  S_MEAN = 9,
+  S_M2 = 10,
+  S_NITER = 11,
+  S_NEXACT = 12,
+  S_SUMEXACT = 13,
+  S_IBAR = 14,
+  S_SIGBAR = 15,
+  S_CHI2 = 16,
+  S_NTOTAL = 17,
+  S_GRAD = 32,
+  S_LEN = 128
+};
+
+enum : int { KIND_FWD = 1, KIND_ADJ = 2, KIND_FUSED = 3 };
+
+struct SampleArgs {
+  const float* table32;  // [d][N][2] (lo, width), FP32
+  const double* edges;   // [d][N+1], FP64
+  double* bins;          // [2][d][N]
+  double* scal;          // S_LEN doubles
+  const double* theta;   // device parameters
+  Key key;
+  uint32_t it, kid;
+  uint32_t nbins;
+  uint32_t ng;        // <= 1: plain
+  uint32_t per_cube;  // nbins / ng when ng divides nbins, else 0
+  uint32_t M;         // cubes
+  uint32_t k;         // samples per cube
+  uint32_t log2G;     // lanes per cube = 1 << log2G
+  uint64_t ncall;     // plain: samples; stratified: k * M
+  uint64_t block_items;  // samples (plain) or cube units (stratified) per block
+};
+
+// LDS layout: grid table first (16-byte entries for FP64), then histogram.
+template <typename T, int D>
+__device__ __forceinline__ void load_table(const SampleArgs& A, typename TabEntry<T>::type* tab) {
+  const int n = D * static_cast<int>(A.nbins);
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    if constexpr (sizeof(T) == 4) {
+      tab[i] = reinterpret_cast<const float2*>(A.table32)[i];
+    } else {
+      const int a = i / A.nbins, j = i - a * A.nbins;
+      const double* e = A.edges + static_cast<size_t>(a) * (A.nbins + 1);
+      tab[i] = make_double2(e[j], e[j + 1] - e[j]);
+    }
+  }
+}
+
+// Map the words of one sample to the point x and the Jacobian.
+template <typename T, int D, bool STRAT>
+__device__ __forceinline__ void make_point(const SampleArgs& A, const typename TabEntry<T>::type* tab,
+                                           const uint32_t (&w)[D], const uint32_t (&cc)[D], int (&j)[D],
+                                           T (&x)[D], T& jac) {
+  const int N = static_cast<int>(A.nbins);
+  const T Nf = static_cast<T>(N);
+  jac = T(1);
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    T dl;
+    if (!STRAT) {
+      bin_plain<T>(w[a], A.nbins, j[a], dl);
+    } else if (A.per_cube) {
+      bin_strat_div<T>(w[a], cc[a], A.per_cube, j[a], dl);
+    } else {
+      bin_strat_gen<T>(w[a], cc[a], A.ng, A.nbins, j[a], dl);
+    }
+    const auto e = tab[a * N + j[a]];
+    x[a] = fma(dl, e.y, e.x);
+    jac *= e.y * Nf;
+  }
+}
+
+template <class F, int KIND>
+__device__ __forceinline__ void accumulate(const SampleArgs& A, double* hist, const int (&j)[F::D],
+                                           typename F::T fv, typename F::T jac,
+                                           const typename F::T (&g)[F::NGRAD + 1], double* acc) {
+  constexpr int D = F::D;
+  constexpr bool HIST = KIND & KIND_FWD, GRAD = KIND & KIND_ADJ;
+  const int N = static_cast<int>(A.nbins);
+  if (HIST) {
+    const auto wv = fv * jac;  // w = f J in the integrand's precision
+    const double wd = static_cast<double>(wv);
+    acc[0] += wd;
+    acc[1] += wd * wd;
+    acc[2] += vfinite(wv) ? 0.0 : 1.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      lds_add(&hist[a * N + j[a]], wd);
+      lds_add(&hist[(D + a) * N + j[a]], wd * wd);
+    }
+  }
+  if (GRAD) {
+#pragma unroll
+    for (int q = 0; q < F::NGRAD; ++q) {
+      const double gq = static_cast<double>(g[q] * jac);
+      acc[3 + q] += gq;
+      acc[3 + F::NGRAD + q] += gq * gq;
+    }
+  }
+}
+
+// Add the block's accumulators to the scalar block and merge the histogram.
+template <class F, int KIND, int NACC>
+__device__ __forceinline__ void flush_block(const SampleArgs& A, double* hist, const double (&acc)[NACC],
+                                            double* red) {
+  constexpr int D = F::D;
+  constexpr bool HIST = KIND & KIND_FWD, GRAD = KIND & KIND_ADJ;
+  constexpr int NG = GRAD ? F::NGRAD : 0;
+  int idx[NACC];
+  idx[0] = S_S1;
+  idx[1] = S_S2;
+  idx[2] = S_NONFIN;
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    idx[3 + q] = S_GRAD + 5 * q;
+    idx[3 + NG + q] = S_GRAD + 5 * q + 1;
+  }
+#pragma unroll
+  for (int q = 3 + 2 * NG; q < NACC; ++q) idx[q] = 0;  // unused tail (stratified V slots)
+  block_sum_to_global<NACC>(acc, red, A.scal, idx);
+  if (HIST) {
+    const int n = 2 * D * static_cast<int>(A.nbins);
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+      const double v = hist[i];
+      if (v != 0.0) global_add(&A.bins[i], v);
+    }
+  }
+}
+
+template <class F, int KIND>
+__device__ __forceinline__ double* setup_lds(const SampleArgs& A, unsigned char* smem,
+                                             typename TabEntry<typename F::T>::type*& tab) {
+  using TE = typename TabEntry<typename F::T>::type;
+  constexpr int D = F::D;
+  tab = reinterpret_cast<TE*>(smem);
+  double* hist = reinterpret_cast<double*>(smem + sizeof(TE) * D * A.nbins);
+  load_table<typename F::T, D>(A, tab);
+  if (KIND & KIND_FWD) {
+    const int n = 2 * D * static_cast<int>(A.nbins);
+    for (int i = threadIdx.x; i < n; i += kBlock) hist[i] = 0.0;
+  }
+  __syncthreads();
+  return hist;
+}
+
+// ---------------------------------------------------------------------------
+// Plain (VEGAS) sampling: block b takes samples [b B, (b+1) B), lanes stride
+// through them.
+// ---------------------------------------------------------------------------
+template <class F, int KIND>
+__global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
+  using T = typename F::T;
+  constexpr int D = F::D;
+  constexpr int NG = (KIND & KIND_ADJ) ? F::NGRAD : 0;
+  constexpr int NACC = 3 + 2 * NG;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[(kBlock / kWave) * NACC];
+  typename TabEntry<T>::type* tab;
+  double* hist = setup_lds<F, KIND>(A, smem, tab);
+
+  F fn;
+  fn.setup(A.theta);
+  double acc[NACC];
+#pragma unroll
+  for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
+
+  const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * A.block_items;
+  const uint64_t b1 = min(b0 + A.block_items, A.ncall);
+  const uint32_t dummy_cc[D] = {};
+  for (uint64_t s = b0 + threadIdx.x; s < b1; s += kBlock) {
+    uint32_t w[D];
+    sample_words<D>(static_cast<uint32_t>(s), A.it, A.kid, A.key, w);
+    int j[D];
+    T x[D], jac;
+    make_point<T, D, false>(A, tab, w, dummy_cc, j, x, jac);
+    T g[F::NGRAD + 1];
+    const T fv = fn.template eval<(KIND & KIND_ADJ) != 0>(x, g);
+    accumulate<F, KIND>(A, hist, j, fv, jac, g, acc);
+  }
+  __syncthreads();
+  flush_block<F, KIND, NACC>(A, hist, acc, red);
+}
+
+// ---------------------------------------------------------------------------
+// Stratified (BASES) sampling.  A unit is (cube c, chunk g); the 2^log2G
+// chunks of one cube sit on adjacent lanes of one wave and split the cube's
+// k samples s = c + t M between them.  After the cube's samples the chunk
+// sums are combined with lane shuffles and the first lane adds the cube's
+// k S2_c - S1_c^2 (and its gradient analogue) to the variance sums.
+// ---------------------------------------------------------------------------
+template <class F, int KIND>
+__global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
+  using T = typename F::T;
+  constexpr int D = F::D;
+  constexpr bool FWD = KIND & KIND_FWD, GRAD = KIND & KIND_ADJ;
+  constexpr int NG = GRAD ? F::NGRAD : 0;
+  constexpr int NACC = 3 + 2 * NG + 1 + NG;  // + V and V_p
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[(kBlock / kWave) * NACC];
+  typename TabEntry<T>::type* tab;
+  double* hist = setup_lds<F, KIND>(A, smem, tab);
+
+  F fn;
+  fn.setup(A.theta);
+  double acc[NACC];
+#pragma unroll
+  for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
+
+  const uint32_t G = 1u << A.log2G;
+  const uint64_t units = static_cast<uint64_t>(A.M) << A.log2G;
+  const uint64_t u0 = static_cast<uint64_t>(blockIdx.x) * A.block_items;
+  const uint64_t u1 = min(u0 + A.block_items, units);
+  const double kd = static_cast<double>(A.k);
+  for (uint64_t base = u0; base < u1; base += kBlock) {
+    const uint64_t u = base + threadIdx.x;
+    const bool active = u < u1;
+    const uint32_t c = static_cast<uint32_t>(u >> A.log2G);
+    const uint32_t gidx = static_cast<uint32_t>(u) & (G - 1);
+    uint32_t cc[D];
+    {
+      uint32_t r = c;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const uint32_t q = r / A.ng;
+        cc[a] = r - q * A.ng;
+        r = q;
+      }
+    }
+    const uint32_t t0 = active ? static_cast<uint32_t>((static_cast<uint64_t>(gidx) * A.k) >> A.log2G) : 0u;
+    const uint32_t t1 =
+        active ? static_cast<uint32_t>((static_cast<uint64_t>(gidx + 1) * A.k) >> A.log2G) : 0u;
+    double c1 = 0.0, c2 = 0.0;
+    double cg1[NG + 1], cg2[NG + 1];
+#pragma unroll
+    for (int q = 0; q < NG; ++q) cg1[q] = cg2[q] = 0.0;
+    for (uint32_t t = t0; t < t1; ++t) {
+      const uint32_t s = c + t * A.M;
+      uint32_t w[D];
+      sample_words<D>(s, A.it, A.kid, A.key, w);
+      int j[D];
+      T x[D], jac;
+      make_point<T, D, true>(A, tab, w, cc, j, x, jac);
+      T g[F::NGRAD + 1];
+      const T fv = fn.template eval<GRAD>(x, g);
+      accumulate<F, KIND>(A, hist, j, fv, jac, g, acc);
+      if (FWD) {
+        const double wd = static_cast<double>(fv * jac);
+        c1 += wd;
+        c2 += wd * wd;
+      }
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        const double gq = static_cast<double>(g[q] * jac);
+        cg1[q] += gq;
+        cg2[q] += gq * gq;
+      }
+    }
+    for (uint32_t off = 1; off < G; off <<= 1) {
+      if (FWD) {
+        c1 += __shfl_xor(c1, off, kWave);
+        c2 += __shfl_xor(c2, off, kWave);
+      }
+#pragma unroll
+      for (int q = 0; q < NG; ++q) {
+        cg1[q] += __shfl_xor(cg1[q], off, kWave);
+        cg2[q] += __shfl_xor(cg2[q], off, kWave);
+      }
+    }
+    if (active && gidx == 0) {
+      if (FWD) acc[3 + 2 * NG] += kd * c2 - c1 * c1;
+#pragma unroll
+      for (int q = 0; q < NG; ++q) acc[4 + 2 * NG + q] += kd * cg2[q] - cg1[q] * cg1[q];
+    }
+  }
+  __syncthreads();
+  // the V slots go through the same block reduction
+  int idx[NACC];
+  idx[0] = S_S1;
+  idx[1] = S_S2;
+  idx[2] = S_NONFIN;
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    idx[3 + q] = S_GRAD + 5 * q;
+    idx[3 + NG + q] = S_GRAD + 5 * q + 1;
+    idx[4 + 2 * NG + q] = S_GRAD + 5 * q + 2;
+  }
+  idx[3 + 2 * NG] = S_V;
+  block_sum_to_global<NACC>(acc, red, A.scal, idx);
+  if (FWD) {
+    const int n = 2 * D * static_cast<int>(A.nbins);
+    for (int i = threadIdx.x; i < n; i += kBlock) {
+      const double v = hist[i];
+      if (v != 0.0) global_add(&A.bins[i], v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-sample dump (tests): the same words, point and integrand as the
+// accumulating kernels, for samples [s0, s0 + count).
+// ---------------------------------------------------------------------------
+struct DumpArgs {
+  SampleArgs A;
+  uint64_t s0, count;
+  uint32_t* words;
+  void* w;
+  void* f;
+  void* jac;
+};
+
+template <class F>
+__global__ __launch_bounds__(kBlock) void k_dump(const DumpArgs P) {
+  using T = typename F::T;
+  constexpr int D = F::D;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const SampleArgs& A = P.A;
+  typename TabEntry<T>::type* tab;
+  (void)setup_lds<F, 0>(A, smem, tab);
+  F fn;
+  fn.setup(A.theta);
+  const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= P.count) return;
+  const uint32_t s = static_cast<uint32_t>(P.s0 + i);
+  uint32_t w[D];
+  sample_words<D>(s, A.it, A.kid, A.key, w);
+  uint32_t cc[D];
+  int j[D];
+  T x[D], jac;
+  if (A.ng > 1) {
+    uint32_t r = s % A.M;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      cc[a] = r % A.ng;
+      r /= A.ng;
+    }
+    make_point<T, D, true>(A, tab, w, cc, j, x, jac);
+  } else {
+#pragma unroll
+    for (int a = 0; a < D; ++a) cc[a] = 0;
+    make_point<T, D, false>(A, tab, w, cc, j, x, jac);
+  }
+  T g[F::NGRAD + 1];
+  const T fv = fn.template eval<false>(x, g);
+  if (P.words) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) P.words[i * D + a] = w[a];
+  }
+  if (P.w) static_cast<T*>(P.w)[i] = fv * jac;
+  if (P.f) static_cast<T*>(P.f)[i] = fv;
+  if (P.jac) static_cast<T*>(P.jac)[i] = jac;
+}
+
+// Kernel entry points of one integrand instantiation.
+struct KernelSet {
+  const void* plain[4];  // indexed by KIND (1 fwd, 2 adj, 3 fused)
+  const void* strat[4];
+  const void* dump;
+  int ngrad;
+  int ntheta;
+  int tab_entry_bytes;
+};
+
+template <class F>
+KernelSet make_kernel_set() {
+  KernelSet s{};
+  s.plain[KIND_FWD] = reinterpret_cast<const void*>(&k_plain<F, KIND_FWD>);
+  s.strat[KIND_FWD] = reinterpret_cast<const void*>(&k_strat<F, KIND_FWD>);
+  if constexpr (F::NGRAD > 0) {
+    s.plain[KIND_ADJ] = reinterpret_cast<const void*>(&k_plain<F, KIND_ADJ>);
+    s.strat[KIND_ADJ] = reinterpret_cast<const void*>(&k_strat<F, KIND_ADJ>);
+    s.plain[KIND_FUSED] = reinterpret_cast<const void*>(&k_plain<F, KIND_FUSED>);
+    s.strat[KIND_FUSED] = reinterpret_cast<const void*>(&k_strat<F, KIND_FUSED>);
+  }
+  s.dump = reinterpret_cast<const void*>(&k_dump<F>);
+  s.ngrad = F::NGRAD;
+  s.ntheta = F::NTHETA;
+  s.tab_entry_bytes = static_cast<int>(sizeof(typename TabEntry<typename F::T>::type));
+  return s;
+}
+
+}  // namespace vmc

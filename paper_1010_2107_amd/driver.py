@@ -1,0 +1,59 @@
+"""Host driver of the iteration loop (step 6 of the six-step structure,
+paper Sec. 3.1): VEGAS runs ITMX iterations; BASES runs ITMX1 grid-
+optimisation iterations and then ITMX2 integration iterations with the grid
+frozen, combining only the latter (Sec. 3.1 and 6.1).  Each iteration is
+stream-ordered library work; the host reads results once at the end unless
+an accuracy target (ACC) asks for a check after every iteration.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .grid import Grid
+
+
+@dataclass
+class Result:
+    I: np.ndarray
+    var: np.ndarray
+    Ibar: float
+    sigbar: float
+    chi2dof: float
+    n_eff: int
+    niter: int
+    grid: Grid
+
+
+def integrate(integrand, dim, nbins, theta, ncall, itmx, seed, alpha=1.5, ng=1, itmx2=0, acc=0.0, fp64=False,
+              grid: Grid | None = None, it0=0, stream=None) -> Result:
+    g = grid if grid is not None else Grid(dim, nbins)
+    assert (g.dim, g.nbins) == (dim, nbins)
+    g.reset(stream)
+    g.stratify(ng)
+    th = g.theta_tensor(theta)
+    total = itmx + itmx2
+    hist = torch.zeros((total, 2), dtype=torch.float64, device=g.device)
+    it, k, n_eff = it0, 0, 0
+    phases = [(itmx, True)] + ([(itmx2, False)] if itmx2 else [])
+    for p, (nit, adapt) in enumerate(phases):
+        if p > 0:
+            g.combine_reset(stream)
+        for _ in range(nit):
+            g.iterate(integrand, th, ncall, seed, it, fp64=fp64, stream=stream)
+            hist[k] = g.scal[L.S_I:L.S_VAR + 1]
+            k += 1
+            it += 1
+            if adapt:
+                g.refine(alpha, stream)
+            if acc > 0:
+                r = g.result()
+                if r["Ibar"] != 0 and r["sigbar"] / abs(r["Ibar"]) < acc:
+                    break
+    r = g.result()
+    h = hist[:k].cpu().numpy()
+    return Result(I=h[:, 0], var=h[:, 1], Ibar=r["Ibar"], sigbar=r["sigbar"], chi2dof=r["chi2dof"],
+                  n_eff=int(r["n_eff"]) * k, niter=r["niter"], grid=g)

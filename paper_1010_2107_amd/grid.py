@@ -1,0 +1,140 @@
+"""Python handle over one grid of libvmc.so.
+
+PyTorch provides the device buffers (caller-owned, bound to the handle) and
+the stream; every step of an iteration runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Grid:
+    """A (dim, nbins) VEGAS grid with its FP64 edges, FP32 table, bin sums
+    and scalar block in device memory (paper Sec. 2: per-axis bins)."""
+
+    def __init__(self, dim: int, nbins: int, device="cuda"):
+        self.dim, self.nbins = int(dim), int(nbins)
+        self.device = torch.device(device)
+        sizes = (ctypes.c_size_t * 4)()
+        L.call("vmc_workspace_sizes", self.dim, self.nbins, sizes)
+        h = ctypes.c_void_p()
+        L.call("vmc_create", self.dim, self.nbins, ctypes.byref(h))
+        self._h = h
+        kw = dict(device=self.device)
+        self.edges = torch.zeros((self.dim, self.nbins + 1), dtype=torch.float64, **kw)
+        self.table = torch.zeros((self.dim, self.nbins, 2), dtype=torch.float32, **kw)
+        self.bins = torch.zeros((2, self.dim, self.nbins), dtype=torch.float64, **kw)
+        self.scal = torch.zeros(L.SCAL_LEN, dtype=torch.float64, **kw)
+        assert self.edges.numel() * 8 == sizes[0] and self.table.numel() * 4 == sizes[1]
+        assert self.bins.numel() * 8 == sizes[2] and self.scal.numel() * 8 == sizes[3]
+        L.call("vmc_bind", h, _ptr(self.edges), _ptr(self.table), _ptr(self.bins), _ptr(self.scal))
+        self.ng = 1
+        self.reset()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and L._lib is not None:
+            L._lib.vmc_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    # ------------------------------------------------------------------ setup
+    def reset(self, stream=None):
+        L.call("vmc_reset", self._h, _stream_ptr(stream))
+
+    def stratify(self, ng: int):
+        L.call("bases_stratify", self._h, int(ng))
+        self.ng = max(int(ng), 1)
+
+    def set_schedule(self, block_samples: int = 0, chunks_per_cube: int = 0):
+        L.call("vmc_set_schedule", self._h, int(block_samples), int(chunks_per_cube))
+
+    def theta_tensor(self, theta) -> torch.Tensor:
+        if isinstance(theta, torch.Tensor):
+            return theta.detach().to(device=self.device, dtype=torch.float64).contiguous()
+        return torch.tensor(np.asarray(theta, dtype=np.float64).reshape(-1), dtype=torch.float64, device=self.device)
+
+    # -------------------------------------------------------------- iteration
+    def _run(self, name, integrand, theta, ncall, seed, it, fp64, stream):
+        th = self.theta_tensor(theta)
+        L.call(name, self._h, int(integrand), _ptr(th if th.numel() else None), th.numel(), int(ncall),
+               int(seed), int(it), L.FLAG_FP64 if fp64 else 0, _stream_ptr(stream))
+        return th
+
+    def iterate(self, integrand, theta, ncall, seed, it, fp64=False, stream=None):
+        """Steps 2-4 of one iteration plus its estimate (stream-ordered)."""
+        return self._run("vmc_iterate", integrand, theta, ncall, seed, it, fp64, stream)
+
+    def adjoint(self, integrand, theta, ncall, seed, it, fp64=False, stream=None):
+        return self._run("vmc_iterate_adjoint", integrand, theta, ncall, seed, it, fp64, stream)
+
+    def fused(self, integrand, theta, ncall, seed, it, fp64=False, stream=None):
+        return self._run("vmc_iterate_fused", integrand, theta, ncall, seed, it, fp64, stream)
+
+    def refine(self, alpha=1.5, stream=None):
+        L.call("vmc_refine", self._h, float(alpha), _stream_ptr(stream))
+
+    def combine_reset(self, stream=None):
+        L.call("vmc_combine_reset", self._h, _stream_ptr(stream))
+
+    def timing(self, enable: bool):
+        """Return (summed ms, launches) of the sample kernels recorded since the
+        last call, then switch recording on or off."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        L.call("vmc_timing", self._h, int(bool(enable)), ctypes.byref(ms), ctypes.byref(n))
+        return ms.value, n.value
+
+    # ---------------------------------------------------------------- results
+    def result(self) -> dict:
+        """Scalar block as a dict (synchronises)."""
+        s = self.scal.cpu().numpy()
+        return dict(S1=s[L.S_S1], S2=s[L.S_S2], V=s[L.S_V], nonfinite=int(s[L.S_NONFINITE]), I=s[L.S_I],
+                    var=s[L.S_VAR], n_eff=int(s[L.S_NEFF]), niter=int(s[L.S_NITER]), Ibar=s[L.S_IBAR],
+                    sigbar=s[L.S_SIGBAR], chi2dof=s[L.S_CHI2])
+
+    def grad_result(self, ngrad: int) -> dict:
+        g = self.scal[L.S_GRAD:L.S_GRAD + 5 * ngrad].cpu().numpy().reshape(ngrad, 5)
+        return dict(gsum=g[:, 0], gsumsq=g[:, 1], gV=g[:, 2], grad=g[:, 3], grad_var=g[:, 4])
+
+    def get_edges(self, stream=None) -> np.ndarray:
+        out = np.zeros((self.dim, self.nbins + 1))
+        L.call("vmc_get_edges", self._h, out.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream))
+        return out
+
+    def set_edges(self, edges, stream=None):
+        e = np.ascontiguousarray(edges, dtype=np.float64)
+        assert e.shape == (self.dim, self.nbins + 1)
+        L.call("vmc_set_edges", self._h, e.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream))
+
+    def dump(self, integrand, theta, ncall, seed, it, s0, count, fp64=False, stream=None):
+        """Per-sample words, w = f J, f and J of samples [s0, s0+count)."""
+        dt = torch.float64 if fp64 else torch.float32
+        kw = dict(device=self.device)
+        words = torch.zeros((count, self.dim), dtype=torch.int32, **kw)
+        w = torch.zeros(count, dtype=dt, **kw)
+        f = torch.zeros(count, dtype=dt, **kw)
+        jac = torch.zeros(count, dtype=dt, **kw)
+        th = self.theta_tensor(theta)
+        L.call("vmc_dump_samples", self._h, int(integrand), _ptr(th if th.numel() else None), th.numel(),
+               int(ncall), int(seed), int(it), L.FLAG_FP64 if fp64 else 0, int(s0), int(count), _ptr(words),
+               _ptr(w), _ptr(f), _ptr(jac), _stream_ptr(stream))
+        return dict(words=words.cpu().numpy().view(np.uint32), w=w.cpu().numpy(), f=f.cpu().numpy(),
+                    jac=jac.cpu().numpy())

@@ -1,0 +1,242 @@
+"""GPU parity of the sample-and-accumulate pass, the estimate, the
+combination and the grid refinement against the FP64 oracle, through the
+C ABI.  Tolerances (stated per test):
+  * random words: bit-exact;
+  * FP64 instantiation (map and integrand in double): 1e-12 relative on every
+    sum, estimate, bin and edge -- only summation order and libm differ;
+  * FP32 integrand with FP64 sums, oracle fed the same grid: 1e-5 relative on
+    S1 and S2 and norm-wise (max-abs error / max-abs value) on the bin sums;
+    the variance is checked at 1e-5 times its cancellation factor
+    (S2/N) / (N var);
+  * FP64 accumulation replayed by the oracle on the GPU's own FP32 weights:
+    1e-12.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1010_2107_amd import workloads as W
+from paper_1010_2107_amd.grid import Grid
+from tests.gpu_util import announce, normwise, rel, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+CASES_FP64 = [
+    # (name, integrand, d, N, theta, ncall, ng)
+    ("gauss_d4_plain", W.GAUSS, 4, 50, (0.5, 0.1), 20_000, 1),
+    ("dgauss_d8_bases", W.DGAUSS, 8, 128, (1 / 3, 2 / 3, 0.1), 4**8 * 3 + 123, 4),
+    ("dgauss_d3_ng3_n50", W.DGAUSS, 3, 50, (0.3, 0.7, 0.12), 27 * 40 + 5, 3),
+    ("axes_d3_plain", W.GAUSS_AXES, 3, 64, (0.3, 0.5, 0.7, 0.15), 100_003, 1),
+    ("linear_d1_n2", W.LINEAR, 1, 2, (), 1001, 1),
+]
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _close(a, b, tol):
+    return rel(a, b) <= tol or abs(a - b) <= tol * 1e-300
+
+
+@pytest.mark.parametrize("case", CASES_FP64, ids=[c[0] for c in CASES_FP64])
+def test_fp64_pipeline_matches_oracle(case):
+    name, iid, d, N, theta, ncall, ng = case
+    announce(f"fp64 pipeline {name}")
+    g = Grid(d, N)
+    g.stratify(ng)
+    edges = O.uniform_edges(d, N)
+    Is, vs = [], []
+    for it in range(4):
+        g.iterate(iid, theta, ncall, 77, it, fp64=True)
+        r = g.result()
+        ref = O.iterate(iid, edges, theta, ncall, 77, it, ng=ng)
+        for key in ("S1", "S2", "I"):
+            assert rel(r[key], ref[key]) <= 1e-12, (it, key, r[key], ref[key])
+        assert r["n_eff"] == ref["n_eff"]
+        assert rel(r["var"], ref["var"]) <= 1e-10, (it, r["var"], ref["var"])
+        if ng > 1:
+            assert rel(r["V"], ref["V"]) <= 1e-10
+        assert normwise(g.bins.cpu().numpy(), ref["bins"]) <= 1e-12
+        Is.append(ref["I"])
+        vs.append(ref["var"])
+        Ib, sb, chi = O.combine(Is, vs)
+        assert rel(r["Ibar"], Ib) <= 1e-12 and rel(r["sigbar"], sb) <= 1e-12
+        if it > 0:
+            assert abs(r["chi2dof"] - chi) <= 1e-9 * max(1.0, chi)
+        g.refine(1.5)
+        edges_ref = O.refine(edges, ref["bins"][1], 1.5)
+        e = g.get_edges()
+        assert np.max(np.abs(e - edges_ref)) <= 1e-12
+        # continue from the oracle's edges so both sides stay on one grid
+        g.set_edges(edges_ref)
+        edges = edges_ref
+
+
+def _adapted_edges(iid, d, N, theta, ncall, ng, iters=3):
+    run = O.integrate(iid, d, N, theta, ncall, iters, 4242, ng=ng)
+    return run.edges
+
+
+@pytest.mark.parametrize("case", [
+    ("gauss_d4_c1", W.GAUSS, 4, 50, (0.5, 0.1), 10_000, 1),
+    ("dgauss_d8_plain", W.DGAUSS, 8, 128, (1 / 3, 2 / 3, 0.1), 400_000, 1),
+    ("dgauss_d8_bases", W.DGAUSS, 8, 128, (1 / 3, 2 / 3, 0.1), 4**8 * 6 + 17, 4),
+    ("axes_d12", W.GAUSS_AXES, 12, 64, tuple(np.linspace(0.3, 0.7, 12)) + (0.2,), 300_001, 1),
+], ids=lambda c: c[0])
+def test_fp32_iteration_matches_oracle_on_same_grid(case):
+    name, iid, d, N, theta, ncall, ng = case
+    announce(f"fp32 grid-synced {name}")
+    edges = _adapted_edges(iid, d, N, theta, min(ncall, 100_000) if ng == 1 else ncall, ng)
+    g = Grid(d, N)
+    g.stratify(ng)
+    g.set_edges(edges)
+    g.iterate(iid, theta, ncall, 1234, 5)
+    r = g.result()
+    ref = O.iterate(iid, edges, theta, ncall, 1234, 5, ng=ng)
+    assert rel(r["S1"], ref["S1"]) <= 1e-5
+    assert rel(r["S2"], ref["S2"]) <= 1e-5
+    assert normwise(g.bins.cpu().numpy()[0], ref["bins"][0]) <= 1e-5
+    assert normwise(g.bins.cpu().numpy()[1], ref["bins"][1]) <= 1e-5
+    n = ref["n_eff"]
+    amp = (ref["S2"] / n) / (n * ref["var"])
+    assert rel(r["var"], ref["var"]) <= 1e-5 * max(1.0, amp)
+    assert r["nonfinite"] == 0
+
+
+def test_random_words_bit_exact():
+    for (d, seed, it, ncall) in ((4, 1234, 0, 10_000), (8, 1234, 19, 5_000_000), (10, 1234, 3, 10_000_000),
+                                 (16, 1234, 19, 50_000_000), (3, 2**63 + 12345, 7, 2_000_000)):
+        announce(f"words d={d} seed={seed} it={it}")
+        g = Grid(d, 64)
+        count = min(ncall, 1 << 20)
+        for s0 in (0, ncall - count):
+            if d in (1, 2, 3, 4, 8):
+                gd = g.dump(W.CONST, (1.0,), ncall, seed, it, s0, count)
+            else:
+                gd = g.dump(W.GAUSS_AXES, tuple([0.5] * d) + (0.1,), ncall, seed, it, s0, count) if d <= 12 else None
+            if gd is None:
+                continue
+            ref = O.eval_samples(W.CONST, O.uniform_edges(d, 64), (1.0,), ncall, seed, it, s0, count)
+            assert np.array_equal(gd["words"], ref["words"]), (d, s0)
+
+
+def test_fp64_accumulators_replayed_on_gpu_weights():
+    announce("replay dgauss d8 plain and bases")
+    for ng, ncall in ((1, 1_000_000), (4, 4**8 * 15)):
+        d, N, theta = 8, 128, (1 / 3, 2 / 3, 0.1)
+        edges = _adapted_edges(W.DGAUSS, d, N, theta, 100_000 if ng == 1 else ncall, ng)
+        g = Grid(d, N)
+        g.stratify(ng)
+        g.set_edges(edges)
+        g.iterate(W.DGAUSS, theta, ncall, 99, 2)
+        r = g.result()
+        dump = g.dump(W.DGAUSS, theta, ncall, 99, 2, 0, r["n_eff"])
+        ref = O.iterate(W.DGAUSS, edges, theta, ncall, 99, 2, ng=ng, w_in=dump["w"])
+        for key in ("S1", "S2", "I"):
+            assert rel(r[key], ref[key]) <= 1e-12, (ng, key)
+        assert rel(r["var"], ref["var"]) <= 1e-10
+        assert normwise(g.bins.cpu().numpy(), ref["bins"]) <= 1e-12
+
+
+def test_refine_matches_oracle_on_given_bins():
+    announce("refine vs oracle")
+    rng = np.random.default_rng(5)
+    for d, N, alpha in ((3, 50, 1.5), (2, 256, 0.7), (4, 2, 1.5), (1, 128, 2.0)):
+        w = rng.gamma(1.0, size=(d, N)) + 0.01
+        edges = np.concatenate([np.zeros((d, 1)), np.cumsum(w, axis=1)], axis=1)
+        edges /= edges[:, -1:]
+        edges[:, -1] = 1.0
+        b2 = rng.gamma(0.4, size=(d, N))
+        if d > 1:
+            b2[1] = 0.0  # all-zero axis stays
+        g = Grid(d, N)
+        g.set_edges(edges)
+        g.bins[1].copy_(torch.from_numpy(b2))
+        g.refine(alpha)
+        got = g.get_edges()
+        ref = O.refine(edges, b2, alpha)
+        assert np.max(np.abs(got - ref)) <= 1e-12
+        tab = g.table.cpu().numpy()
+        assert np.array_equal(tab[..., 0], ref[:, :-1].astype(np.float32))
+        assert np.array_equal(tab[..., 1], np.diff(ref, axis=1).astype(np.float32))
+
+
+def test_schedule_invariance():
+    announce("schedule invariance")
+    d, N, theta = 8, 128, (1 / 3, 2 / 3, 0.1)
+    for ng, ncall, scheds in ((1, 777_777, [(0, 0), (256, 0), (4096, 0), (65536, 0)]),
+                              (4, 4**8 * 20 + 3, [(0, 0), (256, 1), (1024, 4), (2048, 16), (256, 64)])):
+        out = []
+        for bs, ch in scheds:
+            g = Grid(d, N)
+            g.stratify(ng)
+            g.set_schedule(bs, ch)
+            g.iterate(W.DGAUSS, theta, ncall, 5, 1)
+            out.append((g.result(), g.bins.cpu().numpy()))
+        r0, b0 = out[0]
+        for r, b in out[1:]:
+            for key in ("S1", "S2", "V", "I"):
+                assert rel(r[key], r0[key]) <= 1e-12
+            assert normwise(b, b0) <= 1e-12
+
+
+def test_edge_cases():
+    announce("edge cases")
+    # smallest call count, ragged tails, two bins, 256 bins, one axis
+    for d, N, ncall in ((1, 2, 2), (1, 256, 1_000_003), (2, 2, 257), (3, 256, 65_537)):
+        g = Grid(d, N)
+        g.iterate(W.LINEAR, (), ncall, 3, 0, fp64=True)
+        r = g.result()
+        ref = O.iterate(W.LINEAR, O.uniform_edges(d, N), (), ncall, 3, 0)
+        assert rel(r["S1"], ref["S1"]) <= 1e-12 and r["n_eff"] == ncall
+        assert normwise(g.bins.cpu().numpy(), ref["bins"]) <= 1e-12
+    # constant integrand: exact, zero variance, combination reports exact mean
+    g = Grid(2, 8)
+    g.iterate(W.CONST, (2.5,), 1000, 1, 0)
+    r = g.result()
+    assert r["I"] == 2.5 and r["var"] == 0.0 and r["Ibar"] == 2.5 and r["sigbar"] == 0.0
+    g.stratify(4)
+    g.iterate(W.CONST, (2.5,), 16 * 5, 1, 1)
+    r = g.result()
+    assert r["I"] == 2.5 and r["var"] == 0.0
+    # all-zero integrand: refine keeps the grid
+    g = Grid(3, 16)
+    e0 = g.get_edges()
+    g.iterate(W.CONST, (0.0,), 5000, 1, 0)
+    g.refine(1.5)
+    assert np.array_equal(g.get_edges(), e0)
+    # non-finite integrand is counted, not hidden
+    g.iterate(W.CONST, (float("nan"),), 5000, 1, 0)
+    assert g.result()["nonfinite"] == 5000
+
+
+def test_error_paths_on_device():
+    from paper_1010_2107_amd import VmcError
+    announce("error paths")
+    g = Grid(4, 50)
+    with pytest.raises(VmcError) as e:
+        g.iterate(W.GAUSS, (0.5,), 1000, 1, 0)
+    assert e.value.name == "VMC_E_PARAMS"
+    with pytest.raises(VmcError) as e:
+        g.iterate(W.GAUSS, (0.5, 0.1), 1, 1, 0)
+    assert e.value.name == "VMC_E_NCALLS"
+    g.stratify(4)
+    with pytest.raises(VmcError) as e:
+        g.iterate(W.GAUSS, (0.5, 0.1), 4**4 + 5, 1, 0)
+    assert e.value.name == "VMC_E_NCALLS"
+    with pytest.raises(VmcError) as e:
+        g.refine(-1.0)
+    assert e.value.name == "VMC_E_INVALID"
+    with pytest.raises(VmcError) as e:
+        g.set_edges(np.tile(np.linspace(0, 1, 51)[::-1], (4, 1)))
+    assert e.value.name == "VMC_E_GRID"
+    g5 = Grid(5, 10)
+    with pytest.raises(VmcError) as e:
+        g5.iterate(W.GAUSS, (0.5, 0.1), 1000, 1, 0)
+    assert e.value.name == "VMC_E_DIM"
+    with pytest.raises(VmcError) as e:
+        g5.adjoint(W.LINEAR, (), 1000, 1, 0)
+    assert e.value.name in ("VMC_E_DIM", "VMC_E_INTEGRAND")
