@@ -22,28 +22,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP32 flops per sample of the sample kernel (census of the FP32 arithmetic in
-# the map and the integrand; FP64 accumulation and integer work excluded).
-# map: fma (2) + width*N (1) + Jacobian product (1) per axis; w = f J (1).
-CENSUS = {
-    "gauss": lambda d: 4 * d + 3 * d + 2 + 1,
-    "dgauss": lambda d: 4 * d + 6 * d + 6 + 1,
-    "axes": lambda d: 4 * d + 3 * d + 2 + 1,
-}
-PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (packed FMA), 256 CU x 2.4 GHz x 256
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (packed FMA): 256 CU x 2.4 GHz x 256 flop/clk
 PEAK_FP32_NONPACKED = 78.6   # the same without packed FP32 (this build disables packed FP32)
-
-
-def census_for(w):
-    from paper_1010_2107_amd import workloads as W
-    if w.integrand == W.GAUSS:
-        return CENSUS["gauss"](w.dim)
-    if w.integrand == W.DGAUSS:
-        return CENSUS["dgauss"](w.dim)
-    if w.integrand == W.GAUSS_AXES:
-        return CENSUS["axes"](w.dim)
-    from paper_1010_2107_amd import census
-    return census.flops_per_sample(w)
 
 
 def run_loop(grid, w, steps, adjoint=False, fused=False):
@@ -140,14 +120,17 @@ def main(argv=None):
         ms_f, kms_f, _ = run_loop(grid, w, steps, fused=True)
         fa = dict(fwd_adj_evals_per_s=n_eff * steps / (ms_a / 1e3), fused_evals_per_s=n_eff * steps / (ms_f / 1e3))
 
-    flops = census_for(w)
+    from paper_1010_2107_amd import census
+    cen = census.for_workload(w)
+    frac_pass = 1.0 - res["n_zero"] / max(n_eff, 1)
+    flops = cen.flops(frac_pass)
     avg_ms = kms / max(nl, 1)
     achieved = flops * n_eff / (avg_ms / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
             "frac_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
-            "kernel": "sample-and-accumulate", "avg_launch_ms": avg_ms, "flops_per_sample": flops,
-            "samples_per_launch": n_eff}
+            "kernel": "sample-and-accumulate (forward)", "avg_launch_ms": avg_ms, "launches": nl,
+            "flops_per_sample": flops, "accepted_fraction": frac_pass, "samples_per_launch": n_eff}
     line = {
         "metric": "integrand evals/s (fwd)", "value": value, "unit": "evals/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",

@@ -81,6 +81,7 @@ extern "C" {
 #define VMC_S_I 4         /* this iteration's estimate I_k                    */
 #define VMC_S_VAR 5       /* its variance                                     */
 #define VMC_S_NEFF 6      /* samples used this iteration                      */
+#define VMC_S_NZERO 7     /* samples with w = 0 (e.g. outside the cuts)       */
 #define VMC_S_IBAR 14     /* combined estimate over the iterations folded in  */
 #define VMC_S_SIGBAR 15   /* its standard deviation                           */
 #define VMC_S_CHI2 16     /* chi^2 per degree of freedom (NaN for one)        */

@@ -17,7 +17,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "vmc.h")
 CONST, LINEAR, GAUSS, DGAUSS, GAUSS_AXES, WJETS, PSVOL = range(7)
 FLAG_FP64 = 1
 
-S_S1, S_S2, S_V, S_NONFINITE, S_I, S_VAR, S_NEFF = 0, 1, 2, 3, 4, 5, 6
+S_S1, S_S2, S_V, S_NONFINITE, S_I, S_VAR, S_NEFF, S_NZERO = 0, 1, 2, 3, 4, 5, 6, 7
 S_NITER, S_IBAR, S_SIGBAR, S_CHI2, S_GRAD, SCAL_LEN = 11, 14, 15, 16, 32, 128
 
 ERRORS = {

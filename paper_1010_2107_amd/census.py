@@ -1,0 +1,104 @@
+"""FP32 flop census of one sample of the sample-and-accumulate kernel.
+
+Counts the FP32 operations of the per-sample algorithm as written in the HIP
+sources (add/sub/mul = 1, fma = 2; a division or a transcendental counts 1
+flop and is also tallied in `trans`; integer work, compares and the FP64
+accumulation are not FP32 flops).  The W + partons integrand has two paths:
+samples that fail the cuts stop before the colour sum; `per_sample(...)`
+returns both and the bench weights them with the measured accepted fraction.
+Where the kernel evaluates a choice both ways (the two Newton branches of
+the mass step), only the branch the algorithm needs is counted.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from itertools import permutations
+
+from . import workloads as W
+
+
+@dataclass
+class Census:
+    flops_pass: int
+    flops_fail: int
+    trans_pass: int
+    trans_fail: int
+
+    def flops(self, frac_pass: float) -> float:
+        return frac_pass * self.flops_pass + (1.0 - frac_pass) * self.flops_fail
+
+
+def cycles(m):
+    """Distinct cyclic orders of m objects (object 0 first, first < last)."""
+    return [(0,) + p for p in permutations(range(1, m)) if p[0] < p[-1]]
+
+
+def cycle_sum_flops(m):
+    """Multiplications of the unrolled cyclic sum after sharing common
+    prefixes of the products, plus the additions."""
+    cyc = cycles(m)
+    prefixes = set()
+    for o in cyc:
+        for L in range(2, m):  # products of the first L edges, L >= 2
+            prefixes.add(o[: L + 1])
+    return len(prefixes) + len(cyc) + (len(cyc) - 1)
+
+
+MAP_PER_AXIS = 5  # delta scale, fma(delta, width, lo), width*N, Jacobian product
+
+
+def _newton_branch_avg(K):
+    if K == 1:
+        return 3, 2
+    iters = 4
+    b1 = 2 + iters * (K + 9) + 1  # start (r/k1, /k)... then K-1+1+3+3+3 per step
+    b2 = 3 + iters * (4 * (K - 1) + 6) + 1
+    return (b1 + b2) / 2.0, 3 + 2 * iters  # flops, trans (start + one division per step)
+
+
+def wjets(n_p: int) -> Census:
+    n = n_p + 2
+    D = 3 * n_p + 4
+    nv = n_p + 1
+    f = t = 0
+    f += MAP_PER_AXIS * D
+    # parton fractions, flux x Jacobian, s^(n-3), boost rapidity
+    f += 17 + (n - 3)
+    t += 4
+    # mass chain: one inverse-CDF solve per mass, then M_i = M_{i-1} sqrt(t)
+    for K in range(n - 2, 0, -1):
+        ff, tt = _newton_branch_avg(K)
+        f += ff + 1
+        t += tt + 1
+    # two-body steps: the first needs no boost, the others boost two vectors
+    f += 17 + (n - 2) * 52
+    t += 3 + (n - 2) * 5
+    # visible particles: pT^2, light-cone components, rapidity, pT, cuts
+    f += 8 * nv
+    t += 4 * nv
+    # Delta R pairs: cos of the threshold angle by a 6-term Horner series
+    f += 20 * nv * (nv - 1) // 2
+    f_fail, t_fail = f + 1, t
+    # accepted samples: scaled invariants, cyclic sum, Breit-Wigner, product
+    m = n_p + 2
+    f += 3 + 4 * n_p + 9 * (n_p * (n_p - 1) // 2) + cycle_sum_flops(m) + 5 + 4 + 1
+    t += 2 + 2 * n_p + n_p * (n_p - 1) // 2 + 1
+    return Census(int(round(f)), int(round(f_fail)), int(t), int(t_fail))
+
+
+def gaussian(integrand: int, d: int) -> Census:
+    if integrand == W.GAUSS or integrand == W.GAUSS_AXES:
+        fl = MAP_PER_AXIS * d + 3 * d + 2 + 1
+        tr = 1
+    elif integrand == W.DGAUSS:
+        fl = MAP_PER_AXIS * d + 6 * d + 6 + 1
+        tr = 2
+    else:
+        fl, tr = MAP_PER_AXIS * d + 1, 0
+    return Census(fl, fl, tr, tr)
+
+
+def for_workload(w) -> Census:
+    if w.integrand == W.WJETS:
+        return wjets((w.dim - 4) // 3)
+    return gaussian(w.integrand, w.dim)

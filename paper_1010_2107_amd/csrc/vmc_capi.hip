@@ -281,7 +281,7 @@ int vmc_iterate(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int nb = 2 * g->d * g->N;
   hipLaunchKernelGGL(k_clear, dim3((nb + kBlock - 1) / kBlock), dim3(kBlock), 0, st, g->bins, nb, g->scal, 0,
-                     S_NONFIN + 1);
+                     S_NZERO + 1);
   HIP_TRY(hipGetLastError(), "k_clear launch");
   rc = launch_sample(g, P, KIND_FWD, st);
   if (rc) return rc;
@@ -318,7 +318,7 @@ int vmc_iterate_fused(vmc_grid_t g, int integrand, const double* theta, int nthe
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int nb = 2 * g->d * g->N;
   hipLaunchKernelGGL(k_clear, dim3((nb + kBlock - 1) / kBlock), dim3(kBlock), 0, st, g->bins, nb, g->scal, 0,
-                     S_NONFIN + 1);
+                     S_NZERO + 1);
   HIP_TRY(hipGetLastError(), "k_clear launch");
   hipLaunchKernelGGL(k_clear, dim3(1), dim3(kBlock), 0, st, g->bins, 0, g->scal, S_GRAD,
                      S_GRAD + 5 * P.ks->ngrad);

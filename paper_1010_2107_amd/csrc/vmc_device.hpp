@@ -110,6 +110,8 @@ struct TabEntry<double> {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float vexp(float x) { return expf(x); }
 __device__ __forceinline__ double vexp(double x) { return exp(x); }
+__device__ __forceinline__ float vexpm1(float x) { return expm1f(x); }
+__device__ __forceinline__ double vexpm1(double x) { return expm1(x); }
 __device__ __forceinline__ float vlog(float x) { return logf(x); }
 __device__ __forceinline__ double vlog(double x) { return log(x); }
 __device__ __forceinline__ float vsqrt(float x) { return sqrtf(x); }

@@ -24,6 +24,7 @@ enum : int {
   S_I = 4,
   S_VAR = 5,
   S_NEFF = 6,
+  S_NZERO = 7,
   S_W = 8,
   S_MEAN = 9,
   S_M2 = 10,
@@ -39,6 +40,10 @@ enum : int {
 };
 
 enum : int { KIND_FWD = 1, KIND_ADJ = 2, KIND_FUSED = 3 };
+
+// per-thread accumulator slots: S1, S2, non-finite count, zero count, then
+// the gradient sums
+constexpr int kA0 = 4;
 
 struct SampleArgs {
   const float* table32;  // [d][N][2] (lo, width), FP32
@@ -110,6 +115,7 @@ __device__ __forceinline__ void accumulate(const SampleArgs& A, double* hist, co
     acc[0] += wd;
     acc[1] += wd * wd;
     acc[2] += vfinite(wv) ? 0.0 : 1.0;
+    acc[3] += (wv == 0) ? 1.0 : 0.0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       lds_add(&hist[a * N + j[a]], wd);
@@ -120,8 +126,8 @@ __device__ __forceinline__ void accumulate(const SampleArgs& A, double* hist, co
 #pragma unroll
     for (int q = 0; q < F::NGRAD; ++q) {
       const double gq = static_cast<double>(g[q] * jac);
-      acc[3 + q] += gq;
-      acc[3 + F::NGRAD + q] += gq * gq;
+      acc[kA0 + q] += gq;
+      acc[kA0 + F::NGRAD + q] += gq * gq;
     }
   }
 }
@@ -137,13 +143,12 @@ __device__ __forceinline__ void flush_block(const SampleArgs& A, double* hist, c
   idx[0] = S_S1;
   idx[1] = S_S2;
   idx[2] = S_NONFIN;
+  idx[3] = S_NZERO;
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
-    idx[3 + q] = S_GRAD + 5 * q;
-    idx[3 + NG + q] = S_GRAD + 5 * q + 1;
+    idx[kA0 + q] = S_GRAD + 5 * q;
+    idx[kA0 + NG + q] = S_GRAD + 5 * q + 1;
   }
-#pragma unroll
-  for (int q = 3 + 2 * NG; q < NACC; ++q) idx[q] = 0;  // unused tail (stratified V slots)
   block_sum_to_global<NACC>(acc, red, A.scal, idx);
   if (HIST) {
     const int n = 2 * D * static_cast<int>(A.nbins);
@@ -179,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
   using T = typename F::T;
   constexpr int D = F::D;
   constexpr int NG = (KIND & KIND_ADJ) ? F::NGRAD : 0;
-  constexpr int NACC = 3 + 2 * NG;
+  constexpr int NACC = kA0 + 2 * NG;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[(kBlock / kWave) * NACC];
   typename TabEntry<T>::type* tab;
@@ -221,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
   constexpr int D = F::D;
   constexpr bool FWD = KIND & KIND_FWD, GRAD = KIND & KIND_ADJ;
   constexpr int NG = GRAD ? F::NGRAD : 0;
-  constexpr int NACC = 3 + 2 * NG + 1 + NG;  // + V and V_p
+  constexpr int NACC = kA0 + 2 * NG + 1 + NG;  // + V and V_p
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[(kBlock / kWave) * NACC];
   typename TabEntry<T>::type* tab;
@@ -294,9 +299,9 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
       }
     }
     if (active && gidx == 0) {
-      if (FWD) acc[3 + 2 * NG] += kd * c2 - c1 * c1;
+      if (FWD) acc[kA0 + 2 * NG] += kd * c2 - c1 * c1;
 #pragma unroll
-      for (int q = 0; q < NG; ++q) acc[4 + 2 * NG + q] += kd * cg2[q] - cg1[q] * cg1[q];
+      for (int q = 0; q < NG; ++q) acc[kA0 + 1 + 2 * NG + q] += kd * cg2[q] - cg1[q] * cg1[q];
     }
   }
   __syncthreads();
@@ -305,13 +310,14 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
   idx[0] = S_S1;
   idx[1] = S_S2;
   idx[2] = S_NONFIN;
+  idx[3] = S_NZERO;
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
-    idx[3 + q] = S_GRAD + 5 * q;
-    idx[3 + NG + q] = S_GRAD + 5 * q + 1;
-    idx[4 + 2 * NG + q] = S_GRAD + 5 * q + 2;
+    idx[kA0 + q] = S_GRAD + 5 * q;
+    idx[kA0 + NG + q] = S_GRAD + 5 * q + 1;
+    idx[kA0 + 1 + 2 * NG + q] = S_GRAD + 5 * q + 2;
   }
-  idx[3 + 2 * NG] = S_V;
+  idx[kA0 + 2 * NG] = S_V;
   block_sum_to_global<NACC>(acc, red, A.scal, idx);
   if (FWD) {
     const int n = 2 * D * static_cast<int>(A.nbins);

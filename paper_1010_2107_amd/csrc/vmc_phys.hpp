@@ -1,0 +1,386 @@
+// vmc_phys.hpp -- physics-shaped integrand: pp -> W(-> e nu) + NP partons.
+//
+// The paper integrates u dbar -> W+(-> mu+ nu) + n gluons over a
+// 3(n+2)-4 dimensional phase space plus 2 parton momentum fractions
+// (Sec. 5, eq. 1).  Its amplitudes (HELAS/HEGET) and PDFs (CTEQ6L1) are
+// replaced by a toy with the same shape:
+//   x0, x1      -> parton fractions: ln xa = L (1 - x0), ln xb = L x0 (1 - x1),
+//                  L = ln tau0, tau0 = ((1 + NP) pTmin)^2 / S, covering
+//                  xa xb >= tau0 once with Jacobian L^2 x0 xa xb;
+//   flux        -> F(xa) F(xb), F(x) = x^-1.5 (1 - x)^3;
+//   x2..x_{D-1} -> n = NP + 2 massless momenta in the partonic rest frame
+//                  with the "RAMBO on diet" construction (Plaetzer,
+//                  arXiv:1308.2922): n-2 mass fractions, then one direction
+//                  (cos theta, phi) per two-body step;
+//   cuts        -> pT > pTmin, |eta_lab| < etamax for partons and e, and
+//                  Delta R > dRmin for every pair of them (nu unconstrained);
+//   |M|^2       -> g^(2 NP) BW(m_enu^2) 2 s^4 sum_sigma 1/prod s_{sigma_i
+//                  sigma_i+1} over the distinct cyclic orders of the coloured
+//                  set {a, b, partons} (Parke-Taylor denominators);
+//   f           -> flux x Jacobian x |M|^2 x V_n(s) / (2 s), with V_n the
+//                  massless n-body phase-space volume.
+// Per-sample arithmetic is in T; constants are prepared in double in setup().
+#pragma once
+
+#include <array>
+#include <utility>
+
+#include "vmc_device.hpp"
+
+namespace vmc {
+
+// ---------------------------------------------------------------------------
+// Distinct cyclic orders of M objects up to rotation and reflection: object
+// 0 first, the other M-1 in every order whose first entry is below its last.
+// Built at compile time; the sum below is fully unrolled, so products of
+// shared prefixes are computed once.
+// ---------------------------------------------------------------------------
+constexpr int factorial(int n) { return n <= 1 ? 1 : n * factorial(n - 1); }
+
+template <int M>
+constexpr int cycle_count() {
+  return factorial(M - 1) / 2;
+}
+
+template <int M>
+constexpr std::array<std::array<int, M>, cycle_count<M>()> make_cycles() {
+  std::array<std::array<int, M>, cycle_count<M>()> out{};
+  std::array<int, M - 1> p{};
+  for (int i = 0; i < M - 1; ++i) p[i] = i + 1;
+  int n = 0;
+  while (true) {
+    if (p[0] < p[M - 2]) {
+      out[n][0] = 0;
+      for (int i = 0; i < M - 1; ++i) out[n][i + 1] = p[i];
+      ++n;
+    }
+    // next lexicographic permutation of p
+    int i = M - 3;
+    while (i >= 0 && p[i] >= p[i + 1]) --i;
+    if (i < 0) break;
+    int j = M - 2;
+    while (p[j] <= p[i]) --j;
+    int t = p[i];
+    p[i] = p[j];
+    p[j] = t;
+    for (int l = i + 1, r = M - 2; l < r; ++l, --r) {
+      t = p[l];
+      p[l] = p[r];
+      p[r] = t;
+    }
+  }
+  return out;
+}
+
+template <int M, typename T, size_t C>
+__device__ __forceinline__ T cycle_product(const T (&y)[M][M]) {
+  constexpr auto tab = make_cycles<M>();
+  T prod = y[tab[C][0]][tab[C][1]];
+#pragma unroll
+  for (int k = 1; k < M; ++k) prod *= y[tab[C][k]][tab[C][(k + 1) % M]];
+  return prod;
+}
+
+template <int M, typename T, size_t... C>
+__device__ __forceinline__ T cycle_sum_impl(const T (&y)[M][M], std::index_sequence<C...>) {
+  return (cycle_product<M, T, C>(y) + ...);
+}
+
+template <int M, typename T>
+__device__ __forceinline__ T cycle_sum(const T (&y)[M][M]) {
+  return cycle_sum_impl<M, T>(y, std::make_index_sequence<cycle_count<M>()>{});
+}
+
+// ---------------------------------------------------------------------------
+// Mass step of RAMBO on diet: the fraction t = M_i^2 / M_{i-1}^2 has CDF
+// F(t) = (k+1) t^k - k t^(k+1), k = n - i.  Inverted by Newton's method: on
+// t for r < 1/2 (start from F ~ (k+1) t^k), and on u = 1 - t otherwise,
+// using 1 - F(1-u) as a polynomial in u without the cancelling low-order
+// terms (start from 1 - F ~ k(k+1) u^2 / 2).  Returns t and u = 1 - t.
+// ---------------------------------------------------------------------------
+template <int K>
+constexpr double binom(int n, int j) {
+  double r = 1;
+  for (int i = 1; i <= j; ++i) r = r * (n - j + i) / i;
+  return r;
+}
+
+// coefficient of u^j in 1 - F(1-u)
+template <int K>
+constexpr double comp_coef(int j) {
+  double c = (j == 0) ? 1.0 : 0.0;
+  c -= (K + 1) * binom<K>(K, j) * ((j & 1) ? -1.0 : 1.0) * (j <= K ? 1.0 : 0.0);
+  c += K * binom<K>(K + 1, j) * ((j & 1) ? -1.0 : 1.0);
+  return c;
+}
+
+template <typename T>
+struct TU {
+  T t, u;
+};
+
+template <int K, typename T>
+__device__ __forceinline__ TU<T> mass_fraction(T r) {
+  if constexpr (K == 1) {
+    const T s = vsqrt(T(1) - r);
+    return TU<T>{r / (T(1) + s), s};
+  } else {
+    constexpr int ITERS = sizeof(T) == 4 ? 4 : 6;
+    const T k1 = T(K + 1), kk = T(K);
+    // branch 1: Newton on t (used when r < 1/2)
+    T tt = r > T(0) ? vexp(vlog(r / k1) / kk) : T(0);
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+      T tk1 = T(1);
+#pragma unroll
+      for (int q = 0; q < K - 1; ++q) tk1 *= tt;
+      const T tk = tk1 * tt;
+      const T F = tk * (k1 - kk * tt);
+      const T dF = kk * k1 * tk1 * (T(1) - tt);
+      const T step = dF > T(0) ? (F - r) / dF : T(0);
+      tt = fmin(fmax(tt - step, T(0)), T(1));
+    }
+    // branch 2: Newton on u = 1 - t (used when r >= 1/2)
+    const T q = T(1) - r;
+    T uu = vsqrt(T(2) * q / (kk * k1));
+#pragma unroll
+    for (int it = 0; it < ITERS; ++it) {
+      T G = T(comp_coef<K>(K + 1)), dG = T((K + 1) * comp_coef<K>(K + 1));
+#pragma unroll
+      for (int j = K; j >= 2; --j) {
+        G = fma(G, uu, T(comp_coef<K>(j)));
+        dG = fma(dG, uu, T(j * comp_coef<K>(j)));
+      }
+      G *= uu * uu;
+      dG *= uu;
+      const T step = dG > T(0) ? (G - q) / dG : T(0);
+      uu = fmin(fmax(uu - step, T(0)), T(1));
+    }
+    const bool lo = r < T(0.5);
+    return TU<T>{lo ? tt : T(1) - uu, lo ? T(1) - tt : uu};
+  }
+}
+
+// Boost v, given in the rest frame of a system of mass M, to the frame
+// where that system has four-momentum (E, P).
+template <typename T>
+__device__ __forceinline__ void boost(const T (&Q)[4], T invM, T invEM, const T (&v)[4], T (&out)[4]) {
+  const T pdot = Q[1] * v[1] + Q[2] * v[2] + Q[3] * v[3];
+  const T e = (Q[0] * v[0] + pdot) * invM;
+  const T f = fma(pdot, invEM, v[0]) * invM;
+  out[0] = e;
+  out[1] = fma(f, Q[1], v[1]);
+  out[2] = fma(f, Q[2], v[2]);
+  out[3] = fma(f, Q[3], v[3]);
+}
+
+__device__ __forceinline__ void vsincospi(float x, float& s, float& c) { sincospif(x, &s, &c); }
+__device__ __forceinline__ void vsincospi(double x, double& s, double& c) { sincospi(x, &s, &c); }
+
+template <typename TT, int NP, bool FULL>
+struct WJetsF {
+  using T = TT;
+  static constexpr int NOUT = NP + 2;  // final-state particles
+  static constexpr int D = 3 * NP + 4;
+  static constexpr int NGRAD = FULL ? 3 : 0;
+  static constexpr int NTHETA = FULL ? 7 : 2;
+  static constexpr int MC = NP + 2;  // coloured: a, b and the partons
+
+  T L, LL, lnS, sqrtS, pre, expo;
+  T M, Mv2, MG, MGpi, M2G2, invM, invG, two_np_over_g, twoMG2;
+  T ptmin2, etamax, dr2;
+
+  __device__ void setup(const double* th) {
+    const double pi = 3.14159265358979323846;
+    const double sS = FULL ? th[3] : th[0];
+    const double ptm = FULL ? th[4] : th[1];
+    const double S = sS * sS;
+    const double tau0 = ((1.0 + NP) * ptm) * ((1.0 + NP) * ptm) / S;
+    const double Ld = log(tau0);
+    // V_n(s) = cV s^(n-2), cV = (2pi)^(4-3n) (pi/2)^(n-1) / ((n-1)! (n-2)!)
+    const double cV = pow(2.0 * pi, 4.0 - 3.0 * NOUT) * pow(pi / 2.0, NOUT - 1) /
+                      (static_cast<double>(factorial(NOUT - 1)) * factorial(NOUT - 2));
+    L = static_cast<T>(Ld);
+    LL = static_cast<T>(Ld * Ld);
+    lnS = static_cast<T>(log(S));
+    sqrtS = static_cast<T>(sS);
+    expo = static_cast<T>(4.0 / MC);
+    ptmin2 = static_cast<T>(ptm * ptm);
+    if (FULL) {
+      const double Md = th[0], Gd = th[1], gd = th[2];
+      // f = flux Jx g^(2NP) BW [2 s^4 sum 1/prod s] cV s^(n-2) / (2 s)
+      pre = static_cast<T>(cV * pow(gd, 2.0 * NP));
+      M = static_cast<T>(Md);
+      Mv2 = static_cast<T>(Md * Md);
+      MG = static_cast<T>(Md * Gd);
+      MGpi = static_cast<T>(Md * Gd / pi);
+      M2G2 = static_cast<T>(Md * Md * Gd * Gd);
+      invM = static_cast<T>(1.0 / Md);
+      invG = static_cast<T>(1.0 / Gd);
+      two_np_over_g = static_cast<T>(2.0 * NP / gd);
+      twoMG2 = static_cast<T>(2.0 * Md * Gd * Gd);
+      etamax = static_cast<T>(th[5]);
+      dr2 = static_cast<T>(th[6] * th[6]);
+    } else {
+      pre = static_cast<T>(cV / 2.0);
+    }
+  }
+
+  template <bool GRAD>
+  __device__ __forceinline__ T eval(const T (&x)[D], T (&g)[NGRAD + 1]) const {
+    // parton fractions and flux x Jacobian = L^2 x0 tau^-1/2 ((1-xa)(1-xb))^3
+    const T la = L * (T(1) - x[0]);
+    const T lb = L * x[0] * (T(1) - x[1]);
+    const T ltau = la + lb;
+    const T h = vexp(T(0.5) * ltau);  // sqrt(tau)
+    const T rs = sqrtS * h;           // sqrt(s)
+    const T shat = rs * rs;
+    const T om = vexpm1(la) * vexpm1(lb);  // (1 - xa)(1 - xb) without cancellation
+    const T fluxjac = LL * x[0] * (om * om * om) / h;
+    T spow = T(1);
+#pragma unroll
+    for (int i = 0; i < NOUT - 3; ++i) spow *= shat;
+    if constexpr (!FULL) {
+      return pre * fluxjac * spow;
+    } else {
+      const T yb = T(0.5) * (la - lb);
+      // ---- RAMBO on diet: masses M_1 = sqrt(s) > M_2 > ... > M_{n-1} > M_n = 0
+      T Mi[NOUT + 1], Ui[NOUT + 1];
+      Mi[1] = rs;
+      Ui[1] = T(0);
+      mass_chain<2>(x, Mi, Ui);
+      Mi[NOUT] = T(0);
+      Ui[NOUT] = T(1);
+      // ---- two-body steps, each boosted by the current Q_i
+      T p[NOUT][4];
+      T Q[4] = {rs, T(0), T(0), T(0)};
+#pragma unroll
+      for (int i = 1; i <= NOUT - 1; ++i) {
+        const T q = T(0.5) * Mi[i] * Ui[i + 1];  // (M_i^2 - M_{i+1}^2) / (2 M_i)
+        const T rc = x[NOUT + 2 * i - 2];
+        const T rp = x[NOUT + 2 * i - 1];
+        const T cth = fma(T(2), rc, T(-1));
+        const T sth = T(2) * vsqrt(rc * (T(1) - rc));
+        T sp, cp;
+        vsincospi(T(2) * rp, sp, cp);
+        const T nx = sth * cp, ny = sth * sp, nz = cth;
+        const T pr[4] = {q, q * nx, q * ny, q * nz};
+        const T qr[4] = {Mi[i] - q, -q * nx, -q * ny, -q * nz};
+        if (i == 1) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            p[0][c] = pr[c];
+            Q[c] = qr[c];
+          }
+        } else {
+          const T iM = T(1) / Mi[i];
+          const T iEM = T(1) / (Q[0] + Mi[i]);
+          T qn[4];
+          boost(Q, iM, iEM, pr, p[i - 1]);
+          boost(Q, iM, iEM, qr, qn);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) Q[c] = qn[c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) p[NOUT - 1][c] = Q[c];
+
+      // ---- visible particles: partons 0..NP-1 and the electron NP
+      constexpr int NV = NP + 1;
+      T pt2[NV], pt[NV], lp[NV], lm[NV], eta[NV];
+      bool pass = true;
+#pragma unroll
+      for (int j = 0; j < NV; ++j) {
+        pt2[j] = p[j][1] * p[j][1] + p[j][2] * p[j][2];
+        const T e = p[j][0], z = p[j][3];
+        // light-cone components E +- pz, the smaller one from pT^2 / larger
+        if (z > T(0)) {
+          lp[j] = e + z;
+          lm[j] = pt2[j] / lp[j];
+        } else {
+          lm[j] = e - z;
+          lp[j] = pt2[j] / lm[j];
+        }
+        eta[j] = T(0.5) * vlog(lp[j] / lm[j]);
+        pt[j] = vsqrt(pt2[j]);
+        pass = pass && (pt2[j] > ptmin2) && (fabs(eta[j] + yb) < etamax);
+      }
+      // Delta R > R: either Delta eta^2 >= R^2, or cos(Delta phi) < cos(phi0)
+      // with phi0 = sqrt(R^2 - Delta eta^2) <= R; cos(phi0) from its Taylor
+      // series in z = phi0^2 (terms to z^6; remainder below 1e-16 for R <= 0.4).
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int j = i + 1; j < NV; ++j) {
+          const T de = eta[i] - eta[j];
+          const T z = dr2 - de * de;
+          T c = T(1.0 / 479001600.0);
+          c = fma(c, -z, T(1.0 / 3628800.0));
+          c = fma(c, -z, T(1.0 / 40320.0));
+          c = fma(c, -z, T(1.0 / 720.0));
+          c = fma(c, -z, T(1.0 / 24.0));
+          c = fma(c, -z, T(1.0 / 2.0));
+          c = fma(c, -z, T(1));
+          const T dot = p[i][1] * p[j][1] + p[i][2] * p[j][2];
+          pass = pass && ((z <= T(0)) || (dot < c * pt[i] * pt[j]));
+        }
+      if (GRAD) {
+        g[0] = g[1] = g[2] = T(0);
+      }
+      if (!pass) return T(0);
+
+      // ---- invariants of the coloured set, scaled: y = s^(4/m) / s_kl
+      const T c = vexp(expo * (ltau + lnS));
+      T y[MC][MC];
+      y[0][1] = y[1][0] = c / shat;
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        const T ya = c / (rs * lm[j]);  // s_aj = sqrt(s) (E - pz)
+        const T yb2 = c / (rs * lp[j]);  // s_bj = sqrt(s) (E + pz)
+        y[0][2 + j] = y[2 + j][0] = ya;
+        y[1][2 + j] = y[2 + j][1] = yb2;
+      }
+#pragma unroll
+      for (int i = 0; i < NP; ++i)
+#pragma unroll
+        for (int j = i + 1; j < NP; ++j) {
+          const T s = fma(lp[i], lm[j], lm[i] * lp[j]) - T(2) * (p[i][1] * p[j][1] + p[i][2] * p[j][2]);
+          y[2 + i][2 + j] = y[2 + j][2 + i] = c / s;
+        }
+#pragma unroll
+      for (int i = 0; i < MC; ++i) y[i][i] = T(0);
+      const T ptsum = cycle_sum<MC, T>(y);
+
+      // ---- Breit-Wigner in m_enu^2 = M_{n-1}^2 (e nu are the last pair)
+      const T m2 = Mi[NOUT - 1] * Mi[NOUT - 1];
+      const T dm = m2 - Mv2;
+      const T invD = T(1) / fma(dm, dm, M2G2);
+      const T bw = MGpi * invD;
+      const T f = ((pre * spow) * fluxjac) * bw * ptsum;
+      if (GRAD) {
+        g[0] = f * (invM - fma(T(-4) * M, dm, twoMG2) * invD);
+        g[1] = f * (invG - T(2) * M * MG * invD);
+        g[2] = f * two_np_over_g;
+      }
+      return f;
+    }
+  }
+
+  // M_i and U_i = 1 - M_i^2 / M_{i-1}^2 for i = I..n-1 from x[2..n-1]
+  template <int I>
+  __device__ __forceinline__ void mass_chain(const T (&x)[D], T (&Mi)[NOUT + 1], T (&Ui)[NOUT + 1]) const {
+    if constexpr (I <= NOUT - 1) {
+      const TU<T> tu = mass_fraction<NOUT - I, T>(x[I]);
+      Mi[I] = Mi[I - 1] * vsqrt(tu.t);
+      Ui[I] = tu.u;
+      mass_chain<I + 1>(x, Mi, Ui);
+    }
+  }
+};
+
+template <typename T, int D>
+using WJets = WJetsF<T, (D - 4) / 3, true>;
+template <typename T, int D>
+using PsVol = WJetsF<T, (D - 4) / 3, false>;
+
+}  // namespace vmc

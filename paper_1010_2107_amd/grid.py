@@ -107,7 +107,7 @@ class Grid:
         """Scalar block as a dict (synchronises)."""
         s = self.scal.cpu().numpy()
         return dict(S1=s[L.S_S1], S2=s[L.S_S2], V=s[L.S_V], nonfinite=int(s[L.S_NONFINITE]), I=s[L.S_I],
-                    var=s[L.S_VAR], n_eff=int(s[L.S_NEFF]), niter=int(s[L.S_NITER]), Ibar=s[L.S_IBAR],
+                    var=s[L.S_VAR], n_eff=int(s[L.S_NEFF]), n_zero=int(s[L.S_NZERO]), niter=int(s[L.S_NITER]), Ibar=s[L.S_IBAR],
                     sigbar=s[L.S_SIGBAR], chi2dof=s[L.S_CHI2])
 
     def grad_result(self, ngrad: int) -> dict:

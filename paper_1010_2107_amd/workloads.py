@@ -52,7 +52,7 @@ C3 = Workload("wjets2_d10_vegas", WJETS, 10, 64, 10_000_000, 15, WJETS_THETA)
 C4 = Workload("wjets4_d16_vegas", WJETS, 16, 64, 50_000_000, 20, WJETS_THETA)
 
 CONFIGS = {w.name: w for w in (C1, C2, C2_PLAIN, C3, C4)}
-DEFAULT_BENCH = C2
+DEFAULT_BENCH = C4
 
 
 def ngrad(w) -> int:
