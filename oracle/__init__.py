@@ -65,6 +65,9 @@ def lib():
     L.orc_eval_samples.argtypes = [c_int, c_int, c_int, dp, c_int, dp, c_int, c_i64, c_u64,
                                    c_u32, c_u32, c_i64, c_i64, u32p, i32p, dp, dp, dp, dp, dp]
     L.orc_refine.argtypes = [c_int, c_int, dp, dp, c_d, dp]
+    L.orc_accumulate_range.argtypes = [c_int, c_int, c_int, dp, dp, c_int, c_i64, c_u64, c_u32, c_u32, c_i64,
+                                       c_i64, dp, ctypes.c_void_p]
+    L.orc_estimate_plain.argtypes = [ctypes.c_void_p, c_i64]
     L.orc_combine.argtypes = [c_int, dp, dp, dp, dp, dp]
     _lib = L
     return L
@@ -237,6 +240,41 @@ def iterate(integrand_id, edges, theta, ncall, seed, it, kid=0, ng=1, want_grad=
         out["gV"] = gg[:, 2].copy()
         out["grad"] = gg[:, 3].copy()
         out["grad_var"] = gg[:, 4].copy()
+    return out
+
+
+def accumulate_range(integrand_id, edges, theta, ncall, seed, it, s0, s1, kid=0):
+    """Plain-mode sums (S1, S2, bins, nonfinite) over samples [s0, s1)."""
+    e = _d(edges)
+    d, n1 = e.shape
+    th = _d(theta)
+    bins = np.zeros((2, d, n1 - 1))
+    res = IterResult()
+    _check(lib().orc_accumulate_range(integrand_id, d, n1 - 1, _ptr(e, ctypes.c_double), _ptr(th, ctypes.c_double),
+                                      th.size, int(ncall), int(seed), int(it), int(kid), int(s0), int(s1),
+                                      _ptr(bins, ctypes.c_double), ctypes.byref(res)), "orc_accumulate_range")
+    return dict(S1=res.S1, S2=res.S2, nonfinite=res.nonfinite, bins=bins)
+
+
+def _range_job(args):
+    return accumulate_range(*args)
+
+
+def iterate_sharded(integrand_id, edges, theta, ncall, seed, it, pool, nshards, kid=0):
+    """Plain-mode iteration with the samples split into nshards contiguous
+    ranges evaluated by `pool` (a multiprocessing pool); the shards' sums are
+    added and the estimate formed from the totals, as a multi-device split of
+    one iteration would do."""
+    bounds = [ncall * i // nshards for i in range(nshards + 1)]
+    jobs = [(integrand_id, edges, theta, ncall, seed, it, bounds[i], bounds[i + 1], kid) for i in range(nshards)]
+    parts = pool.map(_range_job, jobs)
+    res = IterResult()
+    res.S1 = sum(p["S1"] for p in parts)
+    res.S2 = sum(p["S2"] for p in parts)
+    res.nonfinite = sum(p["nonfinite"] for p in parts)
+    lib().orc_estimate_plain(ctypes.byref(res), int(ncall))
+    out = {f: getattr(res, f) for f, _ in IterResult._fields_}
+    out["bins"] = sum(p["bins"] for p in parts)
     return out
 
 

@@ -674,6 +674,41 @@ int orc_iterate(int id, int d, int nbins, const double *edges, int ng,
     return ORC_OK;
 }
 
+int orc_accumulate_range(int id, int d, int nbins, const double *edges, const double *theta, int ntheta,
+                         int64_t ncall, uint64_t seed, uint32_t it, uint32_t kid, int64_t s0, int64_t s1,
+                         double *bins, orc_iter_result *res)
+{
+    problem pb;
+    int rc = setup_problem(&pb, id, d, nbins, edges, 1, theta, ntheta, ncall, seed, it, kid);
+    if (rc) return rc;
+    if (s0 < 0 || s1 < s0 || s1 > ncall) return ORC_E_INVALID;
+    size_t nb = (size_t)d * (size_t)nbins;
+    memset(bins, 0, 2 * nb * sizeof(double));
+    memset(res, 0, sizeof *res);
+    int32_t j[ORC_MAXD];
+    double x[ORC_MAXD], jac;
+    for (int64_t s = s0; s < s1; ++s) {
+        double w = eval_sample(&pb, (uint32_t)s, NULL, j, x, &jac, NULL, NULL);
+        if (!isfinite(w)) res->nonfinite++;
+        res->S1 += w;
+        res->S2 += w * w;
+        for (int a = 0; a < d; ++a) {
+            bins[(size_t)a * nbins + j[a]] += w;
+            bins[nb + (size_t)a * nbins + j[a]] += w * w;
+        }
+    }
+    res->n_eff = s1 - s0;
+    return ORC_OK;
+}
+
+void orc_estimate_plain(orc_iter_result *res, int64_t ncall)
+{
+    double N = (double)ncall;
+    res->n_eff = ncall;
+    res->I = res->S1 / N;
+    res->var = (res->S2 / N - res->I * res->I) / (N - 1.0);
+}
+
 int orc_eval_samples(int id, int d, int nbins, const double *edges, int ng,
                      const double *theta, int ntheta, int64_t ncall, uint64_t seed,
                      uint32_t it, uint32_t kid, int64_t s0, int64_t count,

@@ -118,6 +118,15 @@ int orc_iterate(int id, int d, int nbins, const double *edges, int ng,
                 uint32_t it, uint32_t kid, double *bins, orc_iter_result *res,
                 double *gsum, const float *w_in);
 
+/* Plain-mode sums over the sample range [s0, s1) only (I and var are left
+ * 0): disjoint ranges added together give exactly the sums of orc_iterate
+ * up to summation order; orc_estimate_plain then forms I and var from the
+ * merged sums of all ncall samples. */
+int orc_accumulate_range(int id, int d, int nbins, const double *edges, const double *theta, int ntheta,
+                         int64_t ncall, uint64_t seed, uint32_t it, uint32_t kid, int64_t s0, int64_t s1,
+                         double *bins, orc_iter_result *res);
+void orc_estimate_plain(orc_iter_result *res, int64_t ncall);
+
 /* Per-sample dump for samples s0 .. s0+count-1 (stratified when ng > 1).
  * Any output pointer may be NULL. */
 int orc_eval_samples(int id, int d, int nbins, const double *edges, int ng,

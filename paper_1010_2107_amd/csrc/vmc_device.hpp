@@ -46,14 +46,45 @@ __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, 
 }
 
 // The D words of sample s: word a is word a%4 of the block with counter
-// (s, a/4, it, kid).
+// (s, a/4, it, kid).  The first round multiplies only c0 = s and c2 = it,
+// which all word groups share, so its products are formed once.
+__device__ __forceinline__ void philox10_from_round1(uint32_t hi0, uint32_t lo0, uint32_t hi1, uint32_t lo1,
+                                                     uint32_t c1, uint32_t c3, Key key, uint32_t (&out)[4]) {
+  uint32_t k0 = key.k0, k1 = key.k1;
+  uint32_t c0 = hi1 ^ c1 ^ k0;
+  uint32_t c2 = hi0 ^ c3 ^ k1;
+  c1 = lo1;
+  c3 = lo0;
+#pragma unroll
+  for (int r = 1; r < 10; ++r) {
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+    const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
+    const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+    const uint32_t x0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ k0;
+    const uint32_t x2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ k1;
+    c1 = static_cast<uint32_t>(pb);
+    c3 = static_cast<uint32_t>(pa);
+    c0 = x0;
+    c2 = x2;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
 template <int D>
 __device__ __forceinline__ void sample_words(uint32_t s, uint32_t it, uint32_t kid, Key key,
                                              uint32_t (&w)[D]) {
+  const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * s;
+  const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * it;
+  const uint32_t hi0 = static_cast<uint32_t>(pa >> 32), lo0 = static_cast<uint32_t>(pa);
+  const uint32_t hi1 = static_cast<uint32_t>(pb >> 32), lo1 = static_cast<uint32_t>(pb);
 #pragma unroll
   for (int g = 0; g < (D + 3) / 4; ++g) {
     uint32_t blk[4];
-    philox10(s, static_cast<uint32_t>(g), it, kid, key, blk);
+    philox10_from_round1(hi0, lo0, hi1, lo1, static_cast<uint32_t>(g), kid, key, blk);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
       if (4 * g + q < D) w[4 * g + q] = blk[q];
@@ -69,7 +100,8 @@ __device__ __forceinline__ void sample_words(uint32_t s, uint32_t it, uint32_t k
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void bin_plain(uint32_t word, uint32_t nbins, int& j, T& delta) {
-  const uint32_t P = ((word >> 9) * 2u + 1u) * nbins;
+  // (2m+1) < 2^24 and nbins <= 256: the 24-bit multiply is exact
+  const uint32_t P = __umul24(((word >> 9) << 1) | 1u, nbins);
   j = static_cast<int>(P >> 24);
   delta = static_cast<T>(static_cast<int>(P & 0xFFFFFFu)) * static_cast<T>(5.9604644775390625e-08);
 }
@@ -78,7 +110,7 @@ template <typename T>
 __device__ __forceinline__ void bin_strat_div(uint32_t word, uint32_t ca, uint32_t per_cube, int& j,
                                               T& delta) {
   // ng divides nbins; per_cube = nbins / ng
-  const uint32_t P = ((word >> 9) * 2u + 1u) * per_cube;
+  const uint32_t P = __umul24(((word >> 9) << 1) | 1u, per_cube);
   j = static_cast<int>(ca * per_cube + (P >> 24));
   delta = static_cast<T>(static_cast<int>(P & 0xFFFFFFu)) * static_cast<T>(5.9604644775390625e-08);
 }
@@ -110,12 +142,32 @@ struct TabEntry<double> {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float vexp(float x) { return expf(x); }
 __device__ __forceinline__ double vexp(double x) { return exp(x); }
+// FP32 reciprocal: the hardware estimate (1 ulp) instead of an IEEE divide
+// sequence; FP64 keeps the correctly rounded division.
+__device__ __forceinline__ float vrcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double vrcp(double x) { return 1.0 / x; }
+// Low-cost forms for quantities whose precision does not reach the result
+// (a Newton starting point, a rapidity compared against a cut): hardware
+// exp2/log2 in FP32, the accurate library functions in FP64.
+__device__ __forceinline__ float vexp_fast(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ double vexp_fast(double x) { return exp(x); }
+__device__ __forceinline__ float vlog_fast(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
+__device__ __forceinline__ double vlog_fast(double x) { return log(x); }
+// sin and cos of 2 pi x for x in [0, 1): the hardware takes its argument in
+// revolutions (absolute error ~1e-7 in FP32).
+__device__ __forceinline__ void vsincos2pi(float x, float& s, float& c) {
+  s = __builtin_amdgcn_sinf(x);
+  c = __builtin_amdgcn_cosf(x);
+}
+__device__ __forceinline__ void vsincos2pi(double x, double& s, double& c) { sincospi(2.0 * x, &s, &c); }
 __device__ __forceinline__ float vexpm1(float x) { return expm1f(x); }
 __device__ __forceinline__ double vexpm1(double x) { return expm1(x); }
 __device__ __forceinline__ float vlog(float x) { return logf(x); }
 __device__ __forceinline__ double vlog(double x) { return log(x); }
-__device__ __forceinline__ float vsqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ float vsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double vsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float vrsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double vrsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ bool vfinite(float x) { return isfinite(x); }
 __device__ __forceinline__ bool vfinite(double x) { return isfinite(x); }
 

@@ -105,7 +105,8 @@ __device__ __forceinline__ void make_point(const SampleArgs& A, const typename T
 template <class F, int KIND>
 __device__ __forceinline__ void accumulate(const SampleArgs& A, double* hist, const int (&j)[F::D],
                                            typename F::T fv, typename F::T jac,
-                                           const typename F::T (&g)[F::NGRAD + 1], double* acc) {
+                                           const typename F::T (&g)[F::NGRAD + 1], double* acc,
+                                           uint32_t* cnt) {
   constexpr int D = F::D;
   constexpr bool HIST = KIND & KIND_FWD, GRAD = KIND & KIND_ADJ;
   const int N = static_cast<int>(A.nbins);
@@ -114,8 +115,8 @@ __device__ __forceinline__ void accumulate(const SampleArgs& A, double* hist, co
     const double wd = static_cast<double>(wv);
     acc[0] += wd;
     acc[1] += wd * wd;
-    acc[2] += vfinite(wv) ? 0.0 : 1.0;
-    acc[3] += (wv == 0) ? 1.0 : 0.0;
+    cnt[0] += vfinite(wv) ? 0u : 1u;
+    cnt[1] += (wv == 0) ? 1u : 0u;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       lds_add(&hist[a * N + j[a]], wd);
@@ -195,6 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
   double acc[NACC];
 #pragma unroll
   for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
+  uint32_t cnt[2] = {0u, 0u};  // non-finite and zero weights
 
   const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * A.block_items;
   const uint64_t b1 = min(b0 + A.block_items, A.ncall);
@@ -207,8 +209,10 @@ __global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
     make_point<T, D, false>(A, tab, w, dummy_cc, j, x, jac);
     T g[F::NGRAD + 1];
     const T fv = fn.template eval<(KIND & KIND_ADJ) != 0>(x, g);
-    accumulate<F, KIND>(A, hist, j, fv, jac, g, acc);
+    accumulate<F, KIND>(A, hist, j, fv, jac, g, acc, cnt);
   }
+  acc[2] = static_cast<double>(cnt[0]);
+  acc[3] = static_cast<double>(cnt[1]);
   __syncthreads();
   flush_block<F, KIND, NACC>(A, hist, acc, red);
 }
@@ -237,6 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
   double acc[NACC];
 #pragma unroll
   for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
+  uint32_t cnt[2] = {0u, 0u};  // non-finite and zero weights
 
   const uint32_t G = 1u << A.log2G;
   const uint64_t units = static_cast<uint64_t>(A.M) << A.log2G;
@@ -274,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
       make_point<T, D, true>(A, tab, w, cc, j, x, jac);
       T g[F::NGRAD + 1];
       const T fv = fn.template eval<GRAD>(x, g);
-      accumulate<F, KIND>(A, hist, j, fv, jac, g, acc);
+      accumulate<F, KIND>(A, hist, j, fv, jac, g, acc, cnt);
       if (FWD) {
         const double wd = static_cast<double>(fv * jac);
         c1 += wd;
@@ -304,6 +309,8 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
       for (int q = 0; q < NG; ++q) acc[kA0 + 1 + 2 * NG + q] += kd * cg2[q] - cg1[q] * cg1[q];
     }
   }
+  acc[2] = static_cast<double>(cnt[0]);
+  acc[3] = static_cast<double>(cnt[1]);
   __syncthreads();
   // the V slots go through the same block reduction
   int idx[NACC];

@@ -123,41 +123,35 @@ template <int K, typename T>
 __device__ __forceinline__ TU<T> mass_fraction(T r) {
   if constexpr (K == 1) {
     const T s = vsqrt(T(1) - r);
-    return TU<T>{r / (T(1) + s), s};
+    return TU<T>{r * vrcp(T(1) + s), s};
   } else {
     constexpr int ITERS = sizeof(T) == 4 ? 4 : 6;
     const T k1 = T(K + 1), kk = T(K);
-    // branch 1: Newton on t (used when r < 1/2)
-    T tt = r > T(0) ? vexp(vlog(r / k1) / kk) : T(0);
+    const bool lo = r < T(0.5);
+    const T q = T(1) - r;  // exact for r >= 1/2
+    // start: F ~ (k+1) t^k for small t, 1 - F ~ k(k+1) u^2 / 2 for small u
+    const T ts = r > T(0) ? vexp_fast(vlog_fast(r * T(1.0 / (K + 1))) * T(1.0 / K)) : T(0);
+    const T us = vsqrt(q * T(2.0 / (K * (K + 1))));
+    T t = lo ? ts : T(1) - us;
+    T u = lo ? T(1) - ts : us;
 #pragma unroll
     for (int it = 0; it < ITERS; ++it) {
       T tk1 = T(1);
 #pragma unroll
-      for (int q = 0; q < K - 1; ++q) tk1 *= tt;
-      const T tk = tk1 * tt;
-      const T F = tk * (k1 - kk * tt);
-      const T dF = kk * k1 * tk1 * (T(1) - tt);
-      const T step = dF > T(0) ? (F - r) / dF : T(0);
-      tt = fmin(fmax(tt - step, T(0)), T(1));
-    }
-    // branch 2: Newton on u = 1 - t (used when r >= 1/2)
-    const T q = T(1) - r;
-    T uu = vsqrt(T(2) * q / (kk * k1));
+      for (int j = 0; j < K - 1; ++j) tk1 *= t;
+      // residual F(t) - r, from t where t is small and as (1-r) - (1-F(1-u))
+      // from u otherwise; 1 - F(1-u) is a polynomial in u starting at u^2
+      T G = T(comp_coef<K>(K + 1));
 #pragma unroll
-    for (int it = 0; it < ITERS; ++it) {
-      T G = T(comp_coef<K>(K + 1)), dG = T((K + 1) * comp_coef<K>(K + 1));
-#pragma unroll
-      for (int j = K; j >= 2; --j) {
-        G = fma(G, uu, T(comp_coef<K>(j)));
-        dG = fma(dG, uu, T(j * comp_coef<K>(j)));
-      }
-      G *= uu * uu;
-      dG *= uu;
-      const T step = dG > T(0) ? (G - q) / dG : T(0);
-      uu = fmin(fmax(uu - step, T(0)), T(1));
+      for (int j = K; j >= 2; --j) G = fma(G, u, T(comp_coef<K>(j)));
+      G *= u * u;
+      const T res = lo ? fma(tk1 * t, k1 - kk * t, -r) : q - G;
+      const T dF = (kk * k1) * tk1 * u;
+      const T step = dF > T(0) ? res * vrcp(dF) : T(0);
+      t = fmin(fmax(t - step, T(0)), T(1));
+      u = fmin(fmax(u + step, T(0)), T(1));
     }
-    const bool lo = r < T(0.5);
-    return TU<T>{lo ? tt : T(1) - uu, lo ? T(1) - tt : uu};
+    return TU<T>{t, u};
   }
 }
 
@@ -174,8 +168,11 @@ __device__ __forceinline__ void boost(const T (&Q)[4], T invM, T invEM, const T 
   out[3] = fma(f, Q[3], v[3]);
 }
 
-__device__ __forceinline__ void vsincospi(float x, float& s, float& c) { sincospif(x, &s, &c); }
-__device__ __forceinline__ void vsincospi(double x, double& s, double& c) { sincospi(x, &s, &c); }
+
+__device__ __forceinline__ int ilogb_(float x) { return __builtin_amdgcn_frexp_expf(x) - 1; }
+__device__ __forceinline__ int ilogb_(double x) { return __builtin_amdgcn_frexp_exp(x) - 1; }
+__device__ __forceinline__ float ldexp_(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
+__device__ __forceinline__ double ldexp_(double x, int e) { return __builtin_amdgcn_ldexp(x, e); }
 
 template <typename TT, int NP, bool FULL>
 struct WJetsF {
@@ -186,7 +183,7 @@ struct WJetsF {
   static constexpr int NTHETA = FULL ? 7 : 2;
   static constexpr int MC = NP + 2;  // coloured: a, b and the partons
 
-  T L, LL, lnS, sqrtS, pre, expo;
+  T L, LL, sqrtS, pre;
   T M, Mv2, MG, MGpi, M2G2, invM, invG, two_np_over_g, twoMG2;
   T ptmin2, etamax, dr2;
 
@@ -202,9 +199,7 @@ struct WJetsF {
                       (static_cast<double>(factorial(NOUT - 1)) * factorial(NOUT - 2));
     L = static_cast<T>(Ld);
     LL = static_cast<T>(Ld * Ld);
-    lnS = static_cast<T>(log(S));
     sqrtS = static_cast<T>(sS);
-    expo = static_cast<T>(4.0 / MC);
     ptmin2 = static_cast<T>(ptm * ptm);
     if (FULL) {
       const double Md = th[0], Gd = th[1], gd = th[2];
@@ -236,7 +231,7 @@ struct WJetsF {
     const T rs = sqrtS * h;           // sqrt(s)
     const T shat = rs * rs;
     const T om = vexpm1(la) * vexpm1(lb);  // (1 - xa)(1 - xb) without cancellation
-    const T fluxjac = LL * x[0] * (om * om * om) / h;
+    const T fluxjac = LL * x[0] * (om * om * om) * vrcp(h);
     T spow = T(1);
 #pragma unroll
     for (int i = 0; i < NOUT - 3; ++i) spow *= shat;
@@ -262,7 +257,7 @@ struct WJetsF {
         const T cth = fma(T(2), rc, T(-1));
         const T sth = T(2) * vsqrt(rc * (T(1) - rc));
         T sp, cp;
-        vsincospi(T(2) * rp, sp, cp);
+        vsincos2pi(rp, sp, cp);
         const T nx = sth * cp, ny = sth * sp, nz = cth;
         const T pr[4] = {q, q * nx, q * ny, q * nz};
         const T qr[4] = {Mi[i] - q, -q * nx, -q * ny, -q * nz};
@@ -273,8 +268,8 @@ struct WJetsF {
             Q[c] = qr[c];
           }
         } else {
-          const T iM = T(1) / Mi[i];
-          const T iEM = T(1) / (Q[0] + Mi[i]);
+          const T iM = vrcp(Mi[i]);
+          const T iEM = vrcp(Q[0] + Mi[i]);
           T qn[4];
           boost(Q, iM, iEM, pr, p[i - 1]);
           boost(Q, iM, iEM, qr, qn);
@@ -287,22 +282,23 @@ struct WJetsF {
 
       // ---- visible particles: partons 0..NP-1 and the electron NP
       constexpr int NV = NP + 1;
-      T pt2[NV], pt[NV], lp[NV], lm[NV], eta[NV];
+      T pt2[NV], pt[NV], rpt2[NV], lp[NV], lm[NV], eta[NV];
       bool pass = true;
 #pragma unroll
       for (int j = 0; j < NV; ++j) {
         pt2[j] = p[j][1] * p[j][1] + p[j][2] * p[j][2];
         const T e = p[j][0], z = p[j][3];
-        // light-cone components E +- pz, the smaller one from pT^2 / larger
-        if (z > T(0)) {
-          lp[j] = e + z;
-          lm[j] = pt2[j] / lp[j];
-        } else {
-          lm[j] = e - z;
-          lp[j] = pt2[j] / lm[j];
-        }
-        eta[j] = T(0.5) * vlog(lp[j] / lm[j]);
-        pt[j] = vsqrt(pt2[j]);
+        // light-cone components E +- pz: the larger directly, the smaller as
+        // pT^2 / larger (massless); rapidity = +-ln(larger / pT)
+        const T big = e + fabs(z);
+        const T small = pt2[j] * vrcp(big);
+        const T rpt = vrsqrt(pt2[j]);
+        const T ya = vlog_fast(big * rpt);
+        lp[j] = z > T(0) ? big : small;
+        lm[j] = z > T(0) ? small : big;
+        eta[j] = z > T(0) ? ya : -ya;
+        pt[j] = pt2[j] * rpt;
+        rpt2[j] = rpt * rpt;
         pass = pass && (pt2[j] > ptmin2) && (fabs(eta[j] + yb) < etamax);
       }
       // Delta R > R: either Delta eta^2 >= R^2, or cos(Delta phi) < cos(phi0)
@@ -314,9 +310,14 @@ struct WJetsF {
         for (int j = i + 1; j < NV; ++j) {
           const T de = eta[i] - eta[j];
           const T z = dr2 - de * de;
-          T c = T(1.0 / 479001600.0);
-          c = fma(c, -z, T(1.0 / 3628800.0));
-          c = fma(c, -z, T(1.0 / 40320.0));
+          T c;
+          if constexpr (sizeof(T) == 8) {
+            c = T(1.0 / 479001600.0);
+            c = fma(c, -z, T(1.0 / 3628800.0));
+            c = fma(c, -z, T(1.0 / 40320.0));
+          } else {
+            c = T(1.0 / 40320.0);  // z^5 term < 3e-11 for z <= 0.16
+          }
           c = fma(c, -z, T(1.0 / 720.0));
           c = fma(c, -z, T(1.0 / 24.0));
           c = fma(c, -z, T(1.0 / 2.0));
@@ -329,14 +330,17 @@ struct WJetsF {
       }
       if (!pass) return T(0);
 
-      // ---- invariants of the coloured set, scaled: y = s^(4/m) / s_kl
-      const T c = vexp(expo * (ltau + lnS));
+      // ---- invariants of the coloured set, scaled: y = c / s_kl with c a power
+      // of two near s^(4/m), so s^4 / prod s = (s^4 / c^m) prod y exactly
+      const int ce = (4 * ilogb_(shat)) / MC;
+      const T c = ldexp_(T(1), ce);
       T y[MC][MC];
-      y[0][1] = y[1][0] = c / shat;
+      const T crs = c * vrcp(rs);
+      y[0][1] = y[1][0] = crs * vrcp(rs);
 #pragma unroll
       for (int j = 0; j < NP; ++j) {
-        const T ya = c / (rs * lm[j]);  // s_aj = sqrt(s) (E - pz)
-        const T yb2 = c / (rs * lp[j]);  // s_bj = sqrt(s) (E + pz)
+        const T ya = crs * lp[j] * rpt2[j];   // c / s_aj, s_aj = sqrt(s) (E - pz)
+        const T yb2 = crs * lm[j] * rpt2[j];  // c / s_bj, s_bj = sqrt(s) (E + pz)
         y[0][2 + j] = y[2 + j][0] = ya;
         y[1][2 + j] = y[2 + j][1] = yb2;
       }
@@ -345,7 +349,7 @@ struct WJetsF {
 #pragma unroll
         for (int j = i + 1; j < NP; ++j) {
           const T s = fma(lp[i], lm[j], lm[i] * lp[j]) - T(2) * (p[i][1] * p[j][1] + p[i][2] * p[j][2]);
-          y[2 + i][2 + j] = y[2 + j][2 + i] = c / s;
+          y[2 + i][2 + j] = y[2 + j][2 + i] = c * vrcp(s);
         }
 #pragma unroll
       for (int i = 0; i < MC; ++i) y[i][i] = T(0);
@@ -354,9 +358,11 @@ struct WJetsF {
       // ---- Breit-Wigner in m_enu^2 = M_{n-1}^2 (e nu are the last pair)
       const T m2 = Mi[NOUT - 1] * Mi[NOUT - 1];
       const T dm = m2 - Mv2;
-      const T invD = T(1) / fma(dm, dm, M2G2);
+      const T invD = vrcp(fma(dm, dm, M2G2));
       const T bw = MGpi * invD;
-      const T f = ((pre * spow) * fluxjac) * bw * ptsum;
+      const T s2 = shat * shat;
+      const T s4c = ldexp_(s2 * s2, -ce * MC);  // s^4 / c^m
+      const T f = ((pre * spow) * fluxjac) * bw * (ptsum * s4c);
       if (GRAD) {
         g[0] = f * (invM - fma(T(-4) * M, dm, twoMG2) * invD);
         g[1] = f * (invG - T(2) * M * MG * invD);

@@ -1,10 +1,14 @@
 """Write tests/golden/wjets_reference.json: reference integrals of the
-W + 2 partons (d=10) and W + 4 partons (d=16) toy cross sections, computed
-with the FP64 oracle only, on seeds independent of the GPU tests' seeds.
+W + 2 partons (d=10) and W + 4 partons (d=16) toy cross sections computed with
+the FP64 oracle only, on a Philox seed independent of the GPU tests' seed.
 
-Each dimension gets NRUNS independent VEGAS runs (different Philox seeds),
-each ITMX iterations of NCALL samples on 64 bins per axis; the runs'
-combined estimates are independent and are merged with weights 1/sigma^2.
+One VEGAS run per dimension at the configuration's own size (ITMX iterations
+of NCALL samples, 64 bins per axis, damping 1.5), each iteration's samples
+split into contiguous ranges over worker processes and summed
+(oracle.iterate_sharded), then refined and combined with weights 1/var.
+Smaller runs (1e6 calls per iteration at d=16) were tried first and gave
+estimates that scatter far beyond their errors: the toy's 1/s_aj terms meet
+the x^-1.5 flux and a thinly sampled grid misses that tail.
 Run:  python tests/golden/make_wjets_reference.py   (about 30 minutes on 8 cores)
 """
 import json
@@ -12,40 +16,40 @@ import math
 import multiprocessing as mp
 import os
 import sys
+import time
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
+import oracle as O  # noqa: E402
+
 THETA = (80.4, 2.1, math.sqrt(4 * math.pi * 0.118), 14000.0, 20.0, 2.5, 0.4)
-NRUNS, NBINS = 8, 64
-NCALL = {10: 5_000_000, 16: 5_000_000}
-ITMX = {10: 10, 16: 15}
+NBINS, ALPHA, SEED = 64, 1.5, 4321
+RUNS = {10: (10_000_000, 15), 16: (50_000_000, 20)}
 
 
-def one(args):
-    import oracle as O
-    d, seed = args
-    run = O.integrate(O.WJETS, d, NBINS, THETA, NCALL[d], ITMX[d], seed)
-    return dict(seed=seed, Ibar=run.Ibar, sigbar=run.sigbar, chi2dof=run.chi2dof)
-
-
-def main():
-    jobs = [(d, 900_000 + 100 * d + r) for d in (10, 16) for r in range(NRUNS)]
-    with mp.Pool(min(8, os.cpu_count() or 1)) as pool:
-        res = pool.map(one, jobs)
-    out = {"theta": THETA, "nbins": NBINS, "runs": NRUNS,
+def main(nproc=8):
+    out = {"theta": THETA, "nbins": NBINS, "alpha": ALPHA, "seed": SEED,
            "note": "written by tests/golden/make_wjets_reference.py from the FP64 oracle only"}
-    for d in (10, 16):
-        rs = [r for (dd, _), r in zip(jobs, res) if dd == d]
-        w = [1 / r["sigbar"] ** 2 for r in rs]
-        I = sum(wi * r["Ibar"] for wi, r in zip(w, rs)) / sum(w)
-        s = sum(w) ** -0.5
-        chi = sum((r["Ibar"] - I) ** 2 / r["sigbar"] ** 2 for r in rs) / (len(rs) - 1)
-        out[str(d)] = {"ncall": NCALL[d], "itmx": ITMX[d], "Ibar": I, "sigbar": s, "chi2dof_between_runs": chi, "runs": rs}
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "wjets_reference.json")
-    with open(path, "w") as f:
-        json.dump(out, f, indent=1)
-    print(json.dumps({k: (v if not isinstance(v, dict) else {kk: vv for kk, vv in v.items() if kk != "runs"})
+    with mp.get_context("fork").Pool(nproc) as pool:
+        for d, (ncall, itmx) in RUNS.items():
+            e = O.uniform_edges(d, NBINS)
+            Is, vs = [], []
+            t0 = time.time()
+            for it in range(itmx):
+                r = O.iterate_sharded(O.WJETS, e, THETA, ncall, SEED, it, pool, 4 * nproc)
+                Is.append(r["I"])
+                vs.append(r["var"])
+                e = O.refine(e, r["bins"][1], ALPHA)
+                print(f"d={d} it={it} I={r['I']:.6g} sd={math.sqrt(r['var']):.3g} ({time.time() - t0:.0f}s)",
+                      flush=True)
+            Ib, sb, chi = O.combine(Is, vs)
+            out[str(d)] = {"ncall": ncall, "itmx": itmx, "Ibar": Ib, "sigbar": sb, "chi2dof": chi,
+                           "I": Is, "var": vs}
+            with open(path, "w") as f:
+                json.dump(out, f, indent=1)
+    print(json.dumps({k: {kk: vv for kk, vv in v.items() if kk not in ("I", "var")} if isinstance(v, dict) else v
                       for k, v in out.items()}, indent=1))
 
 

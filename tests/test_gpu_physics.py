@@ -165,7 +165,10 @@ def test_configuration_against_oracle_reference(w):
     path = os.path.join(HERE, "golden", "wjets_reference.json")
     if not os.path.exists(path):
         pytest.skip("reference integrals not generated (tests/golden/make_wjets_reference.py)")
-    ref = json.load(open(path))[str(w.dim)]
+    allref = json.load(open(path))
+    if str(w.dim) not in allref:
+        pytest.skip(f"no reference for d={w.dim} yet")
+    ref = allref[str(w.dim)]
     announce(f"end-to-end {w.name}")
     r = integrate(w.integrand, w.dim, w.nbins, w.theta, w.ncall, w.itmx, w.seed, alpha=w.alpha)
     z = abs(r.Ibar - ref["Ibar"]) / np.hypot(r.sigbar, ref["sigbar"])

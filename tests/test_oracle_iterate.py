@@ -185,3 +185,19 @@ def test_error_codes():
         O.iterate(O.GAUSS, e, [0.5, 0.1], 4 * 4 + 3, 1, 0, ng=4)  # k < 2
     with pytest.raises(O.OracleError):
         O.iterate(O.WJETS, O.uniform_edges(9, 8), [0] * 7, 100, 1, 0)  # bad physics dimension
+
+
+def test_sharded_iteration_equals_single_iteration():
+    """Disjoint sample ranges summed give the single-range sums (the CPU
+    rehearsal of splitting one iteration's samples across devices)."""
+    import multiprocessing as mp
+    rng = np.random.default_rng(12)
+    e = _grid(rng, 4, 16)
+    th = [0.4, 0.6, 0.15]
+    ref = O.iterate(O.DGAUSS, e, th, 100_003, 5, 2)
+    with mp.get_context("fork").Pool(3) as pool:
+        got = O.iterate_sharded(O.DGAUSS, e, th, 100_003, 5, 2, pool, 5)
+    for key in ("S1", "S2", "I", "var"):
+        assert abs(got[key] - ref[key]) <= 1e-12 * abs(ref[key])
+    assert np.allclose(got["bins"], ref["bins"], rtol=1e-12, atol=0)
+    assert got["n_eff"] == ref["n_eff"]
