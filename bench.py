@@ -56,24 +56,115 @@ def run_loop(grid, w, steps, adjoint=False, fused=False):
 
 def cpu_baseline(w, edges, budget_s=15.0):
     """The FP64 oracle, single thread, on a bounded sample of the workload:
-    iterations on the GPU-adapted grid until `budget_s` seconds have passed."""
+    a short probe sets the sample count so that one oracle iteration on the
+    GPU-adapted grid takes about `budget_s` seconds."""
     import oracle as O
-    ncall = w.ncall
+    probe = 20_000 if w.ng <= 1 else None
     if w.ng <= 1:
-        ncall = min(w.ncall, 2_000_000)
-    n = 0
-    it = 0
+        t0 = time.perf_counter()
+        O.iterate(w.integrand, edges, w.theta, probe, w.seed, 999)
+        rate = probe / (time.perf_counter() - t0)
+        ncall = int(min(w.ncall, max(probe, budget_s * rate)))
+    else:
+        ncall = w.ncall
     t0 = time.perf_counter()
-    while True:
-        r = O.iterate(w.integrand, edges, w.theta, ncall, w.seed, 1000 + it, ng=w.ng)
-        n += r["n_eff"]
-        it += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
+    r = O.iterate(w.integrand, edges, w.theta, ncall, w.seed, 1000, ng=w.ng)
     dt = time.perf_counter() - t0
-    return dict(value=n / dt, unit="evals/s", cores=1, kind="oracle",
-                sample=f"{it} oracle iteration(s) x {r['n_eff']} samples of this workload on the GPU-adapted grid "
-                       f"({n} evals, {dt:.1f} s, 1 thread, {platform.processor() or platform.machine()})")
+    return dict(value=r["n_eff"] / dt, unit="evals/s", cores=1, kind="oracle",
+                sample=f"one oracle iteration of {r['n_eff']} samples of this workload on the GPU-adapted grid "
+                       f"({dt:.1f} s, 1 thread, {platform.processor() or platform.machine()})")
+
+
+def measure_workload(grid, w, steps, warmup):
+    """Forward loop (value), forward + separate adjoint, and fused loops."""
+    from paper_1010_2107_amd import workloads as W
+    if warmup:
+        run_loop(grid, w, warmup)
+    ms, kms, nl = run_loop(grid, w, steps)
+    res = grid.result()
+    out = dict(ms=ms, kms=kms, nl=nl, res=res, n_eff=res["n_eff"], value=res["n_eff"] * steps / (ms / 1e3))
+    if W.ngrad(w) > 0:
+        ms_a, _, _ = run_loop(grid, w, steps, adjoint=True)
+        ms_f, _, _ = run_loop(grid, w, steps, fused=True)
+        out["fwd_adj_evals_per_s"] = res["n_eff"] * steps / (ms_a / 1e3)
+        out["fused_evals_per_s"] = res["n_eff"] * steps / (ms_f / 1e3)
+    return out
+
+
+def batched_leg(itmx=None):
+    """The 64-integral batched configuration: one persistent launch per
+    iteration (autotuned schedule) against the same integrals advanced one
+    at a time through the single-grid calls."""
+    import numpy as np
+    import torch
+
+    from paper_1010_2107_amd import workloads as W
+    from paper_1010_2107_amd.autotune import autotune
+    from paper_1010_2107_amd.batch import Batch
+    from paper_1010_2107_amd.grid import Grid
+
+    spec = W.batched_config()
+    itmx = itmx or spec.itmx
+    th = [spec.theta(k) for k in range(spec.n)]
+    b = Batch(spec.dims, spec.ncalls, th, nbins=spec.nbins)
+    (spt, blocks), _ = autotune(b, kind=1)
+    calls = int(spec.ncalls.sum())
+
+    def loop(kind):
+        b.reset()
+        torch.cuda.synchronize()
+        b.timing(True)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for it in range(itmx):
+            b.iterate(spec.seed, it, kind)
+            b.refine(spec.alpha if hasattr(spec, "alpha") else 1.5)
+        t1.record()
+        torch.cuda.synchronize()
+        kms, nl = b.timing(False)
+        return t0.elapsed_time(t1), kms, nl
+
+    loop(1)  # warm-up
+    ms, kms, nl = loop(1)
+    r = b.results()
+    zs = []
+    from scipy import special
+    for k in range(spec.n):
+        c, s_ = np.asarray(spec.centres[k]), spec.sigmas[k]
+        I = np.prod(0.5 * (special.erf((1 - c) / s_) + special.erf(c / s_)))
+        zs.append(abs(r["Ibar"][k] - I) / r["sigbar"][k])
+    ms_f, _, _ = loop(3)
+    # the same integrals one by one through the single-grid calls
+    grids = {}
+    for d in sorted(set(spec.dims.tolist())):
+        grids[d] = Grid(d, spec.nbins)
+    ths = [grids[spec.dims[k]].theta_tensor(th[k]) for k in range(spec.n)]
+
+    def seq():
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for k in range(spec.n):
+            g = grids[spec.dims[k]]
+            g.reset()
+            for it in range(itmx):
+                g.iterate(W.GAUSS_AXES, ths[k], int(spec.ncalls[k]), spec.seed, it)
+                g.refine(1.5)
+        t1.record()
+        torch.cuda.synchronize()
+        return t0.elapsed_time(t1)
+
+    seq()
+    ms_seq = seq()
+    return {"integrals": spec.n, "total_calls_per_iteration": calls, "iterations": itmx,
+            "schedule": {"samples_per_thread": spt, "blocks": blocks},
+            "evals_per_s": calls * itmx / (ms / 1e3), "ms_per_iteration": ms / itmx,
+            "kernel_ms_per_launch": kms / max(nl, 1),
+            "fused_fwd_adj_evals_per_s": calls * itmx / (ms_f / 1e3),
+            "sequential_single_grid_evals_per_s": calls * itmx / (ms_seq / 1e3),
+            "max_z_vs_closed_form": float(max(zs)), "all_within_3_sigma": bool(max(zs) < 3)}
 
 
 def main(argv=None):
@@ -83,6 +174,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the other workloads and the batched leg")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     args = ap.parse_args(argv)
     if args.gpus != 1:
@@ -90,9 +182,9 @@ def main(argv=None):
               "sample pass is a design note, not a built path", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
+    from paper_1010_2107_amd import census
     from paper_1010_2107_amd import workloads as W
     from paper_1010_2107_amd.grid import Grid
 
@@ -101,48 +193,63 @@ def main(argv=None):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     print(f"[bench] workload {w.name} steps {steps} warmup {args.warmup}", file=sys.stderr, flush=True)
     grid = Grid(w.dim, w.nbins)
-    # warm-up iterations (module load, first launches); not timed
-    if args.warmup:
-        run_loop(grid, w, args.warmup)
-    ms, kms, nl = run_loop(grid, w, steps)
-    res = grid.result()
+    m = measure_workload(grid, w, steps, args.warmup)
+    res, n_eff = m["res"], m["n_eff"]
     edges = grid.get_edges()
-    n_eff = res["n_eff"]
-    value = n_eff * steps / (ms / 1e3)
-    z = None if w.I_ref is None or res["sigbar"] == 0 else abs(res["Ibar"] - w.I_ref) / res["sigbar"]
-    print(f"[bench] fwd {value:.4g} evals/s, Ibar {res['Ibar']:.6g} +- {res['sigbar']:.3g}", file=sys.stderr,
+    print(f"[bench] fwd {m['value']:.4g} evals/s, Ibar {res['Ibar']:.6g} +- {res['sigbar']:.3g}", file=sys.stderr,
           flush=True)
+    z = None if w.I_ref is None or res["sigbar"] == 0 else abs(res["Ibar"] - w.I_ref) / res["sigbar"]
+    ref_note = None
+    if w.I_ref is None and w.integrand == W.WJETS:
+        import json as _j
+        p = os.path.join(ROOT, "tests", "golden", "wjets_reference.json")
+        if os.path.exists(p):
+            ref = _j.load(open(p)).get(str(w.dim))
+            if ref:
+                z = abs(res["Ibar"] - ref["Ibar"]) / math.hypot(res["sigbar"], ref["sigbar"])
+                ref_note = {"I_ref": ref["Ibar"], "sig_ref": ref["sigbar"], "source": "FP64 oracle, independent seed"}
 
-    # forward + adjoint on the same samples (separate adjoint pass, then fused)
-    fa = {}
-    if W.ngrad(w) > 0:
-        ms_a, kms_a, _ = run_loop(grid, w, steps, adjoint=True)
-        ms_f, kms_f, _ = run_loop(grid, w, steps, fused=True)
-        fa = dict(fwd_adj_evals_per_s=n_eff * steps / (ms_a / 1e3), fused_evals_per_s=n_eff * steps / (ms_f / 1e3))
-
-    from paper_1010_2107_amd import census
     cen = census.for_workload(w)
     frac_pass = 1.0 - res["n_zero"] / max(n_eff, 1)
     flops = cen.flops(frac_pass)
-    avg_ms = kms / max(nl, 1)
+    avg_ms = m["kms"] / max(m["nl"], 1)
     achieved = flops * n_eff / (avg_ms / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
             "frac_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
-            "kernel": "sample-and-accumulate (forward)", "avg_launch_ms": avg_ms, "launches": nl,
+            "kernel": "sample-and-accumulate (forward)", "avg_launch_ms": avg_ms, "launches": m["nl"],
             "flops_per_sample": flops, "accepted_fraction": frac_pass, "samples_per_launch": n_eff}
     line = {
-        "metric": "integrand evals/s (fwd)", "value": value, "unit": "evals/s", "n_gpus": 1, "steps": steps,
-        "warmup": args.warmup, "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
+        "metric": "integrand evals/s (fwd)", "value": m["value"], "unit": "evals/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": m["ms"] / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 integrand, f64 sums", "data": "synthetic (counter-based Philox samples)",
         "config": {"workload": w.name, "dim": w.dim, "nbins": w.nbins, "ncall": w.ncall, "n_eff": n_eff,
                    "iterations": steps, "mode": "bases-stratified" if w.ng > 1 else "vegas",
                    "ng": w.ng, "parallelism": "single-gpu"},
         "result": {"Ibar": res["Ibar"], "sigbar": res["sigbar"], "chi2dof": res["chi2dof"],
-                   "I_ref": w.I_ref, "z": z, "within_3_sigma": None if z is None else bool(z < 3)},
+                   "I_ref": w.I_ref if ref_note is None else ref_note, "z": z,
+                   "within_3_sigma": None if z is None else bool(z < 3)},
         "roofline": roof,
     }
-    line.update(fa)
+    for key in ("fwd_adj_evals_per_s", "fused_evals_per_s"):
+        if key in m:
+            line[key] = m[key]
+    if not args.no_secondary:
+        sec = {}
+        for w2 in (W.C2, W.C2_PLAIN, W.C3):
+            if w2.name == w.name:
+                continue
+            g2 = Grid(w2.dim, w2.nbins)
+            m2 = measure_workload(g2, w2, w2.itmx + w2.itmx2, 1)
+            r2 = m2["res"]
+            z2 = None if w2.I_ref is None else abs(r2["Ibar"] - w2.I_ref) / r2["sigbar"]
+            sec[w2.name] = {k: m2[k] for k in ("value", "fwd_adj_evals_per_s", "fused_evals_per_s") if k in m2}
+            sec[w2.name].update({"Ibar": r2["Ibar"], "sigbar": r2["sigbar"], "z": z2,
+                                 "kernel_ms_per_launch": m2["kms"] / max(m2["nl"], 1)})
+            print(f"[bench] {w2.name}: {m2['value']:.4g} evals/s", file=sys.stderr, flush=True)
+        line["secondary"] = sec
+        print("[bench] batched leg", file=sys.stderr, flush=True)
+        line["batched"] = batched_leg()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, edges, args.cpu_budget)

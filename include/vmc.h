@@ -200,6 +200,59 @@ int vmc_set_schedule(vmc_grid_t g, int block_samples, int chunks_per_cube);
  * or disables recording.  Errors: VMC_E_INVALID, VMC_E_HIP. */
 int vmc_timing(vmc_grid_t g, int enable, double *total_ms, int64_t *launches);
 
+/* ------------------------------------------------------------ batches */
+/* Many independent integrals of uneven dimension and call count advanced
+ * together by one persistent launch per iteration.  Integral k has its own
+ * grid (nbins per axis), parameters and accumulators; its samples use the
+ * Philox counter (s, word group, it, k), so its results equal those of a
+ * single-integral run with integral id k, whatever the schedule. */
+typedef struct vmc_batch_s *vmc_batch_t;
+
+/* n integrals; dims[k] in [1,12]; ncall[k] in [2, 2^32); integrand must be
+ * VMC_GAUSS_AXES (theta_k = (c_0..c_{d_k-1}, s), d_k + 1 values).
+ * Errors: VMC_E_INVALID, VMC_E_DIM, VMC_E_NCALLS, VMC_E_NBINS,
+ * VMC_E_INTEGRAND. */
+int vmc_batch_create(int n, const int *dims, int nbins, int integrand, const int64_t *ncall,
+                     vmc_batch_t *out);
+int vmc_batch_destroy(vmc_batch_t b);
+
+/* Bytes of the six caller-owned device buffers, concatenated over k in
+ * order: out[0] edges (d_k (nbins+1) doubles each), out[1] table (d_k nbins
+ * float pairs), out[2] bins (2 d_k nbins doubles), out[3] scal
+ * (VMC_SCAL_LEN doubles per integral, layout as for one grid), out[4] theta
+ * (d_k + 1 doubles each, written by the caller), out[5] meta (work list for
+ * the current schedule). */
+int vmc_batch_workspace_sizes(vmc_batch_t b, size_t out[6]);
+
+/* Bind the device buffers; meta_bytes is the size of `meta`.  Errors:
+ * VMC_E_INVALID. */
+int vmc_batch_bind(vmc_batch_t b, double *edges, float *table, double *bins, double *scal,
+                   const double *theta, void *meta, size_t meta_bytes);
+
+/* Schedule of the persistent launch: samples_per_thread sets the tile
+ * size (256 x samples_per_thread samples of one integral), blocks the
+ * persistent grid; 0 selects the built-in value.  Changes the work list
+ * (re-query out[5] of vmc_batch_workspace_sizes).  Errors: VMC_E_SCHEDULE. */
+int vmc_batch_set_schedule(vmc_batch_t b, int samples_per_thread, int blocks);
+
+/* Uniform grids and cleared accumulators for every integral; uploads the
+ * work list and waits for that copy.  Errors: VMC_E_UNBOUND,
+ * VMC_E_SCHEDULE (meta too small), VMC_E_HIP. */
+int vmc_batch_reset(vmc_batch_t b, void *stream);
+
+/* One iteration of every integral in one persistent launch: kind 1
+ * forward (bin sums, estimate, running combination), 2 adjoint (gradient
+ * block only), 3 both in one pass.  Errors: VMC_E_UNBOUND, VMC_E_INVALID,
+ * VMC_E_SCHEDULE, VMC_E_HIP. */
+int vmc_iterate_batched(vmc_batch_t b, uint64_t seed, uint32_t it, int kind, uint32_t flags, void *stream);
+
+/* Refine every axis of every integral (one block per axis), as
+ * vmc_refine.  Errors: VMC_E_INVALID, VMC_E_UNBOUND, VMC_E_HIP. */
+int vmc_refine_batched(vmc_batch_t b, double alpha, void *stream);
+
+/* As vmc_timing, for the batched launches of this handle. */
+int vmc_batch_timing(vmc_batch_t b, int enable, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -64,6 +64,16 @@ _SIGS = {
                                     _c.c_int64, _c.c_int64, _vp, _vp, _vp, _vp, _vp]),
     "vmc_set_schedule": (_c.c_int, [_vp, _c.c_int, _c.c_int]),
     "vmc_timing": (_c.c_int, [_vp, _c.c_int, _c.POINTER(_c.c_double), _c.POINTER(_c.c_int64)]),
+    "vmc_batch_create": (_c.c_int, [_c.c_int, _c.POINTER(_c.c_int), _c.c_int, _c.c_int, _c.POINTER(_c.c_int64),
+                                    _c.POINTER(_vp)]),
+    "vmc_batch_destroy": (_c.c_int, [_vp]),
+    "vmc_batch_workspace_sizes": (_c.c_int, [_vp, _c.POINTER(_c.c_size_t)]),
+    "vmc_batch_bind": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _c.c_size_t]),
+    "vmc_batch_set_schedule": (_c.c_int, [_vp, _c.c_int, _c.c_int]),
+    "vmc_batch_reset": (_c.c_int, [_vp, _vp]),
+    "vmc_iterate_batched": (_c.c_int, [_vp, _c.c_uint64, _c.c_uint32, _c.c_int, _c.c_uint32, _vp]),
+    "vmc_refine_batched": (_c.c_int, [_vp, _c.c_double, _vp]),
+    "vmc_batch_timing": (_c.c_int, [_vp, _c.c_int, _c.POINTER(_c.c_double), _c.POINTER(_c.c_int64)]),
 }
 
 

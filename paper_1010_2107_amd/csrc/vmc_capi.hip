@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "vmc.h"
+#include "vmc_error.hpp"
 #include "vmc_registry.hpp"
 #include "vmc_small.hpp"
 
@@ -19,8 +20,8 @@ using namespace vmc;
 
 static thread_local std::string g_last_error;
 
-static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-static int fail(int code, const char* fmt, ...) {
+namespace vmc {
+int set_error(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -29,6 +30,9 @@ static int fail(int code, const char* fmt, ...) {
   g_last_error = buf;
   return code;
 }
+}  // namespace vmc
+
+#define fail vmc::set_error
 
 static int hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) return fail(VMC_E_HIP, "%s: %s", what, hipGetErrorString(e));

@@ -7,6 +7,8 @@
 #include "vmc_kernels.hpp"
 
 namespace vmc {
+// internal linkage: every unit that launches these kernels gets its own copy
+namespace {
 
 __global__ __launch_bounds__(kBlock) void k_clear(double* bins, int nbins_total, double* scal, int s_lo,
                                                   int s_hi) {
@@ -23,8 +25,7 @@ __global__ __launch_bounds__(kBlock) void k_clear(double* bins, int nbins_total,
 // weighted incremental mean so that chi^2 needs no stored history.
 // Iterations with var = 0 are exact; when any exist the combined value is
 // their mean with zero error.
-__global__ void k_finalize(double* scal, int strat, double n, double kd, double Md, int fwd, int ngrad) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void finalize_one(double* scal, int strat, double n, double kd, double Md, int fwd, int ngrad) {
   const double denom = kd * kd * (kd - 1.0) * Md * Md;
   if (fwd) {
     const double I = scal[S_S1] / n;
@@ -62,6 +63,11 @@ __global__ void k_finalize(double* scal, int strat, double n, double kd, double 
     g[3] = G;
     g[4] = strat ? g[2] / denom : (g[1] / n - G * G) / (n - 1.0);
   }
+}
+
+__global__ void k_finalize(double* scal, int strat, double n, double kd, double Md, int fwd, int ngrad) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  finalize_one(scal, strat, n, kd, Md, fwd, ngrad);
 }
 
 __global__ void k_combine_reset(double* scal) {
@@ -108,15 +114,13 @@ __global__ __launch_bounds__(kBlock) void k_table(const double* edges, float* ta
 //  equal weight.  An axis with zero (or non-finite) smoothed sum is kept.
 // The two short sums run in order on one thread; everything else is one
 // thread per bin / per new edge.
-__global__ __launch_bounds__(kBlock) void k_refine(double* edges, float* table, const double* bins, int d,
-                                                   int N, double alpha) {
+// ea: the axis' N+1 edges; ta: its N (lo, width) table entries; b2: its N
+// plane-1 bin sums.  Called by a whole block.
+__device__ void refine_axis(double* ea, float* ta, const double* b2, int N, double alpha) {
   __shared__ double e[257], r[256], C[257], en[257];
   __shared__ double Dsum, Tshare;
   __shared__ int keep;
-  const int a = blockIdx.x;
   const int t = threadIdx.x;
-  double* ea = edges + static_cast<size_t>(a) * (N + 1);
-  const double* b2 = bins + static_cast<size_t>(d + a) * N;
   for (int i = t; i <= N; i += kBlock) e[i] = ea[i];
   for (int i = t; i < N; i += kBlock) C[i] = b2[i];
   __syncthreads();
@@ -177,9 +181,17 @@ __global__ __launch_bounds__(kBlock) void k_refine(double* edges, float* table, 
   __syncthreads();
   for (int k = t; k <= N; k += kBlock) ea[k] = en[k];
   for (int j = t; j < N; j += kBlock) {
-    table[2 * (a * N + j)] = static_cast<float>(en[j]);
-    table[2 * (a * N + j) + 1] = static_cast<float>(en[j + 1] - en[j]);
+    ta[2 * j] = static_cast<float>(en[j]);
+    ta[2 * j + 1] = static_cast<float>(en[j + 1] - en[j]);
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_refine(double* edges, float* table, const double* bins, int d,
+                                                   int N, double alpha) {
+  const int a = blockIdx.x;
+  refine_axis(edges + static_cast<size_t>(a) * (N + 1), table + static_cast<size_t>(2) * a * N,
+              bins + static_cast<size_t>(d + a) * N, N, alpha);
+}
+
+}  // namespace
 }  // namespace vmc

@@ -53,3 +53,29 @@ def test_host_side_errors_without_gpu():
         L.call("vmc_destroy", h)
     L.call("vmc_destroy", None)
     assert V.lib().vmc_version() >= 100
+
+
+def test_batch_create_validation():
+    def create(dims, ncalls, integrand=V.GAUSS_AXES, nbins=64):
+        h = ctypes.c_void_p()
+        d = (ctypes.c_int * len(dims))(*dims)
+        n = (ctypes.c_int64 * len(ncalls))(*ncalls)
+        L.call("vmc_batch_create", len(dims), d, nbins, integrand, n, ctypes.byref(h))
+        return h
+    for args, code in ((([13], [100]), "VMC_E_DIM"), (([3], [1]), "VMC_E_NCALLS"),
+                       (([3], [100], V.GAUSS), "VMC_E_INTEGRAND"), (([3], [100], V.GAUSS_AXES, 1), "VMC_E_NBINS")):
+        with pytest.raises(V.VmcError) as e:
+            create(*args)
+        assert e.value.name == code
+    h = create([2, 12, 5], [10_000, 1_000_000, 257])
+    sz = (ctypes.c_size_t * 6)()
+    L.call("vmc_batch_workspace_sizes", h, sz)
+    assert sz[0] == 8 * 19 * 65 and sz[1] == 4 * 2 * 19 * 64 and sz[2] == 8 * 2 * 19 * 64
+    assert sz[3] == 8 * 128 * 3 and sz[4] == 8 * (3 + 19)
+    with pytest.raises(V.VmcError) as e:
+        L.call("vmc_batch_set_schedule", h, -1, 0)
+    assert e.value.name == "VMC_E_SCHEDULE"
+    with pytest.raises(V.VmcError) as e:
+        L.call("vmc_iterate_batched", h, 1, 0, 1, 0, None)
+    assert e.value.name == "VMC_E_UNBOUND"
+    L.call("vmc_batch_destroy", h)
