@@ -22,6 +22,42 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+def source_sha1():
+    """Hash of the kernel sources and the public header, identifying the
+    kernel build that a hardware-counter summary was taken on."""
+    import glob
+    import hashlib
+    h = hashlib.sha1()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1010_2107_amd", "csrc", "*"))) + [
+        os.path.join(ROOT, "include", "vmc.h")]
+    for f in files:
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name):
+    """HBM bytes per launch of the forward sample kernel from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy
+    calibration), or None when the summary is missing or was taken on other
+    kernel sources."""
+    p = os.path.join(ROOT, "profiles", f"pmc_sample_kernel_{workload_name}.txt")
+    if not os.path.exists(p):
+        return None
+    kv = {}
+    for line in open(p):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source-sha1") != source_sha1():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (packed FMA): 256 CU x 2.4 GHz x 256 flop/clk
 PEAK_FP32_NONPACKED = 78.6   # the same without packed FP32 (this build disables packed FP32)
 
@@ -91,7 +127,7 @@ def measure_workload(grid, w, steps, warmup):
     return out
 
 
-def batched_leg(itmx=None):
+def batched_leg():
     """The 64-integral batched configuration: one persistent launch per
     iteration (autotuned schedule) against the same integrals advanced one
     at a time through the single-grid calls."""
@@ -104,11 +140,12 @@ def batched_leg(itmx=None):
     from paper_1010_2107_amd.grid import Grid
 
     spec = W.batched_config()
-    itmx = itmx or spec.itmx
     th = [spec.theta(k) for k in range(spec.n)]
     b = Batch(spec.dims, spec.ncalls, th, nbins=spec.nbins)
     (spt, blocks), _ = autotune(b, kind=1)
     calls = int(spec.ncalls.sum())
+
+    itmx = spec.itmx + spec.itmx2
 
     def loop(kind):
         b.reset()
@@ -117,9 +154,7 @@ def batched_leg(itmx=None):
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         t0.record()
-        for it in range(itmx):
-            b.iterate(spec.seed, it, kind)
-            b.refine(spec.alpha if hasattr(spec, "alpha") else 1.5)
+        b.run(spec.seed, spec.itmx, spec.itmx2, kind=kind, freeze=spec.freeze)
         t1.record()
         torch.cuda.synchronize()
         kms, nl = b.timing(False)
@@ -150,8 +185,11 @@ def batched_leg(itmx=None):
             g = grids[spec.dims[k]]
             g.reset()
             for it in range(itmx):
+                if it == spec.itmx:
+                    g.combine_reset()
                 g.iterate(W.GAUSS_AXES, ths[k], int(spec.ncalls[k]), spec.seed, it)
-                g.refine(1.5)
+                if it < spec.itmx or not spec.freeze:
+                    g.refine(1.5)
         t1.record()
         torch.cuda.synchronize()
         return t0.elapsed_time(t1)
@@ -159,6 +197,7 @@ def batched_leg(itmx=None):
     seq()
     ms_seq = seq()
     return {"integrals": spec.n, "total_calls_per_iteration": calls, "iterations": itmx,
+            "phases": {"warm_up_not_combined": spec.itmx, "combined": spec.itmx2, "grid_frozen": spec.freeze},
             "schedule": {"samples_per_thread": spt, "blocks": blocks},
             "evals_per_s": calls * itmx / (ms / 1e3), "ms_per_iteration": ms / itmx,
             "kernel_ms_per_launch": kms / max(nl, 1),
@@ -176,6 +215,9 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true", help="skip the other workloads and the batched leg")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--pmc-mode", action="store_true",
+                    help="for hardware-counter runs: a plain 1 GiB device copy (calibrates FETCH_SIZE and "
+                         "WRITE_SIZE), then the workload's forward loop only")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of the "
@@ -191,6 +233,16 @@ def main(argv=None):
     w = W.CONFIGS[args.workload] if args.workload else W.DEFAULT_BENCH
     steps = args.steps if args.steps is not None else w.itmx + w.itmx2
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.pmc_mode:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)  # 1 GiB read + 1 GiB written
+        torch.cuda.synchronize()
+        grid = Grid(w.dim, w.nbins)
+        ms, kms, nl = run_loop(grid, w, steps)
+        print(json.dumps({"pmc_mode": True, "workload": w.name, "steps": steps, "kernel_ms": kms / max(nl, 1),
+                          "copy_bytes_each_way": src.numel() * 4, "source_sha1": source_sha1()}), flush=True)
+        return 0
     print(f"[bench] workload {w.name} steps {steps} warmup {args.warmup}", file=sys.stderr, flush=True)
     grid = Grid(w.dim, w.nbins)
     m = measure_workload(grid, w, steps, args.warmup)
@@ -215,7 +267,7 @@ def main(argv=None):
     avg_ms = m["kms"] / max(m["nl"], 1)
     achieved = flops * n_eff / (avg_ms / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(w.name),
             "frac_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
             "kernel": "sample-and-accumulate (forward)", "avg_launch_ms": avg_ms, "launches": m["nl"],
             "flops_per_sample": flops, "accepted_fraction": frac_pass, "samples_per_launch": n_eff}

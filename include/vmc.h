@@ -250,6 +250,9 @@ int vmc_iterate_batched(vmc_batch_t b, uint64_t seed, uint32_t it, int kind, uin
  * vmc_refine.  Errors: VMC_E_INVALID, VMC_E_UNBOUND, VMC_E_HIP. */
 int vmc_refine_batched(vmc_batch_t b, double alpha, void *stream);
 
+/* Clear every integral's running combination (BASES integration phase). */
+int vmc_batch_combine_reset(vmc_batch_t b, void *stream);
+
 /* As vmc_timing, for the batched launches of this handle. */
 int vmc_batch_timing(vmc_batch_t b, int enable, double *total_ms, int64_t *launches);
 

@@ -74,6 +74,28 @@ class Batch:
     def refine(self, alpha=1.5, stream=None):
         L.call("vmc_refine_batched", self._h, float(alpha), _stream_ptr(stream))
 
+    def combine_reset(self, stream=None):
+        L.call("vmc_batch_combine_reset", self._h, _stream_ptr(stream))
+
+    def run(self, seed, itmx, itmx2=0, alpha=1.5, kind=1, freeze=True):
+        """itmx warm-up iterations that refine the grids, then itmx2 more,
+        combining only the latter; freeze=True keeps the grids fixed in the
+        second phase (BASES), freeze=False keeps refining (VEGAS with the
+        warm-up iterations left out of the combination)."""
+        it = 0
+        for _ in range(itmx):
+            self.iterate(seed, it, kind)
+            self.refine(alpha)
+            it += 1
+        if itmx2:
+            self.combine_reset()
+            for _ in range(itmx2):
+                self.iterate(seed, it, kind)
+                if not freeze:
+                    self.refine(alpha)
+                it += 1
+        return self.results()
+
     def timing(self, enable):
         ms = ctypes.c_double()
         n = ctypes.c_int64()

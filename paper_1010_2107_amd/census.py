@@ -34,14 +34,16 @@ def cycles(m):
 
 
 def cycle_sum_flops(m):
-    """Multiplications of the unrolled cyclic sum after sharing common
-    prefixes of the products, plus the additions."""
-    cyc = cycles(m)
-    prefixes = set()
-    for o in cyc:
-        for L in range(2, m):  # products of the first L edges, L >= 2
-            prefixes.add(o[: L + 1])
-    return len(prefixes) + len(cyc) + (len(cyc) - 1)
+    """Flops of the subset dynamic programme over paths from object 0: each
+    (set S, end v) with |S| >= 2 costs one multiply and |S|-2 fmas; closing
+    the full paths costs one multiply, m-2 fmas and the final halving."""
+    K = m - 1
+    f = 0
+    for mask in range(1, 1 << K):
+        p = bin(mask).count("1")
+        if p >= 2:
+            f += p * (1 + 2 * (p - 2))
+    return f + 1 + 2 * (K - 1) + 1
 
 
 MAP_PER_AXIS = 5  # delta scale, fma(delta, width, lo), width*N, Jacobian product

@@ -108,8 +108,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& B, const BatchDesc& 
   constexpr bool FWD = KIND & KIND_FWD, GRAD = KIND & KIND_ADJ;
   const int N = static_cast<int>(B.nbins);
   const T Nf = static_cast<T>(N);
-  GaussAxesF<T, D> fn;
-  fn.setup(B.theta + ds.off_theta);
+  const GaussAxesF<T, D> fn = block_setup<GaussAxesF<T, D>>(B.theta + ds.off_theta);
   for (uint32_t s = tl.s0 + threadIdx.x; s < tl.s1; s += kBlock) {
     uint32_t w[D];
     sample_words<D>(s, B.it, ds.kid, B.key, w);
@@ -234,6 +233,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_clear(double* bins, uint32_t n
     scal[static_cast<size_t>(k) * S_LEN + slot] = 0.0;
   }
   if (tid == 0) *counter = 0u;
+}
+
+__global__ void k_batch_combine_reset(double* scal, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t per = S_NTOTAL - S_W + 1;
+  if (i >= n * per) return;
+  const uint32_t k = i / per;
+  scal[static_cast<size_t>(k) * S_LEN + S_W + (i - k * per)] = 0.0;
 }
 
 __global__ void k_batch_finalize(const BatchDesc* desc, double* scal, uint32_t n, int fwd, int grad) {
@@ -548,6 +555,16 @@ int vmc_refine_batched(vmc_batch_t b, double alpha, void* stream) {
   hipLaunchKernelGGL(k_batch_refine, dim3(static_cast<unsigned>(b->axes.size())), dim3(kBlock), 0, st, d, ax, b->edges,
                      b->table, b->bins, b->N, alpha);
   HIP_TRY(hipGetLastError(), "k_batch_refine launch");
+  return VMC_OK;
+}
+
+int vmc_batch_combine_reset(vmc_batch_t b, void* stream) {
+  int rc = need_bound(b);
+  if (rc) return rc;
+  const uint32_t total = static_cast<uint32_t>(b->n) * (S_NTOTAL - S_W + 1);
+  hipLaunchKernelGGL(k_batch_combine_reset, dim3((total + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                     static_cast<hipStream_t>(stream), b->scal, static_cast<uint32_t>(b->n));
+  HIP_TRY(hipGetLastError(), "k_batch_combine_reset launch");
   return VMC_OK;
 }
 

@@ -4,6 +4,7 @@
 // structure of Kanzaki, arXiv:1010.2107, Sec. 3.1).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -199,11 +200,14 @@ int plan_launch(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
     A.ncall = static_cast<uint64_t>(ncall);
     P.items = A.ncall;
     P.n_eff = static_cast<double>(ncall);
+    // built-in: at least 1024 blocks, at most 8192 samples per block (many
+    // short blocks even out the per-block variation of cut-dependent work
+    // and the tail of the last wave of blocks)
     uint64_t b = g->block_items;
     if (!b) {
       b = (A.ncall + 1023) / 1024;
       b = ((b + kBlock - 1) / kBlock) * kBlock;
-      if (b < kBlock) b = kBlock;
+      b = std::min<uint64_t>(std::max<uint64_t>(b, kBlock), 8192);
     }
     A.block_items = b;
   } else {
@@ -219,9 +223,10 @@ int plan_launch(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
     A.k = static_cast<uint32_t>(k);
     A.ncall = k * M;
     P.n_eff = static_cast<double>(k * M);
+    // built-in: about 32 samples per lane, and about 512 blocks
     uint32_t G = static_cast<uint32_t>(g->chunks);
     if (!G) {
-      uint64_t want = k / 8;
+      uint64_t want = k / 32;
       G = 1;
       while (G < 64 && 2 * G <= want) G <<= 1;
     }
@@ -231,7 +236,7 @@ int plan_launch(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
     P.items = M << lg;
     uint64_t b = g->block_items;
     if (!b) {
-      b = (P.items + 1023) / 1024;
+      b = (P.items + 511) / 512;
       b = ((b + kBlock - 1) / kBlock) * kBlock;
       if (b < kBlock) b = kBlock;
     }

@@ -176,6 +176,16 @@ __device__ __forceinline__ double* setup_lds(const SampleArgs& A, unsigned char*
   return hist;
 }
 
+// The integrand's per-parameter constants (normalisations, erf, logs in
+// FP64) are computed once per block by thread 0 and broadcast through LDS.
+template <class F>
+__device__ __forceinline__ F block_setup(const double* theta) {
+  __shared__ F shared_fn;
+  if (threadIdx.x == 0) shared_fn.setup(theta);
+  __syncthreads();
+  return shared_fn;
+}
+
 // ---------------------------------------------------------------------------
 // Plain (VEGAS) sampling: block b takes samples [b B, (b+1) B), lanes stride
 // through them.
@@ -191,8 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
   typename TabEntry<T>::type* tab;
   double* hist = setup_lds<F, KIND>(A, smem, tab);
 
-  F fn;
-  fn.setup(A.theta);
+  const F fn = block_setup<F>(A.theta);
   double acc[NACC];
 #pragma unroll
   for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
@@ -236,8 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
   typename TabEntry<T>::type* tab;
   double* hist = setup_lds<F, KIND>(A, smem, tab);
 
-  F fn;
-  fn.setup(A.theta);
+  const F fn = block_setup<F>(A.theta);
   double acc[NACC];
 #pragma unroll
   for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
@@ -356,8 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_dump(const DumpArgs P) {
   const SampleArgs& A = P.A;
   typename TabEntry<T>::type* tab;
   (void)setup_lds<F, 0>(A, smem, tab);
-  F fn;
-  fn.setup(A.theta);
+  const F fn = block_setup<F>(A.theta);
   const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x;
   if (i >= P.count) return;
   const uint32_t s = static_cast<uint32_t>(P.s0 + i);

@@ -22,73 +22,52 @@
 // Per-sample arithmetic is in T; constants are prepared in double in setup().
 #pragma once
 
-#include <array>
-#include <utility>
-
 #include "vmc_device.hpp"
 
 namespace vmc {
 
 // ---------------------------------------------------------------------------
-// Distinct cyclic orders of M objects up to rotation and reflection: object
-// 0 first, the other M-1 in every order whose first entry is below its last.
-// Built at compile time; the sum below is fully unrolled, so products of
-// shared prefixes are computed once.
+// Colour-ordered denominators: the sum over the (M-1)!/2 distinct cyclic
+// orders (up to rotation and reflection) of M objects.
 // ---------------------------------------------------------------------------
 constexpr int factorial(int n) { return n <= 1 ? 1 : n * factorial(n - 1); }
 
-template <int M>
-constexpr int cycle_count() {
-  return factorial(M - 1) / 2;
-}
-
-template <int M>
-constexpr std::array<std::array<int, M>, cycle_count<M>()> make_cycles() {
-  std::array<std::array<int, M>, cycle_count<M>()> out{};
-  std::array<int, M - 1> p{};
-  for (int i = 0; i < M - 1; ++i) p[i] = i + 1;
-  int n = 0;
-  while (true) {
-    if (p[0] < p[M - 2]) {
-      out[n][0] = 0;
-      for (int i = 0; i < M - 1; ++i) out[n][i + 1] = p[i];
-      ++n;
-    }
-    // next lexicographic permutation of p
-    int i = M - 3;
-    while (i >= 0 && p[i] >= p[i + 1]) --i;
-    if (i < 0) break;
-    int j = M - 2;
-    while (p[j] <= p[i]) --j;
-    int t = p[i];
-    p[i] = p[j];
-    p[j] = t;
-    for (int l = i + 1, r = M - 2; l < r; ++l, --r) {
-      t = p[l];
-      p[l] = p[r];
-      p[r] = t;
-    }
-  }
-  return out;
-}
-
-template <int M, typename T, size_t C>
-__device__ __forceinline__ T cycle_product(const T (&y)[M][M]) {
-  constexpr auto tab = make_cycles<M>();
-  T prod = y[tab[C][0]][tab[C][1]];
-#pragma unroll
-  for (int k = 1; k < M; ++k) prod *= y[tab[C][k]][tab[C][(k + 1) % M]];
-  return prod;
-}
-
-template <int M, typename T, size_t... C>
-__device__ __forceinline__ T cycle_sum_impl(const T (&y)[M][M], std::index_sequence<C...>) {
-  return (cycle_product<M, T, C>(y) + ...);
-}
-
+// Sum over the distinct cyclic orders of prod y along the cycle, by dynamic
+// programming over subsets: P[S][v] is the sum of the products along all
+// paths that start at object 0, visit exactly the objects in S and end at v.
+// Closing every full path back to 0 counts each undirected cycle twice (once
+// per direction), hence the factor 1/2.  For six objects this is 165
+// multiply-adds instead of ~290 operations for the 60 explicit products.
 template <int M, typename T>
 __device__ __forceinline__ T cycle_sum(const T (&y)[M][M]) {
-  return cycle_sum_impl<M, T>(y, std::make_index_sequence<cycle_count<M>()>{});
+  constexpr int K = M - 1;  // objects 1..M-1, bit b <-> object b+1
+  constexpr int FULL = (1 << K) - 1;
+  T P[1 << K][K];
+#pragma unroll
+  for (int mask = 1; mask <= FULL; ++mask) {
+#pragma unroll
+    for (int v = 0; v < K; ++v) {
+      if (!((mask >> v) & 1)) continue;
+      const int prev = mask ^ (1 << v);
+      if (prev == 0) {
+        P[mask][v] = y[0][v + 1];
+      } else {
+        T acc = T(0);
+        bool first = true;
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+          if (!((prev >> u) & 1)) continue;
+          acc = first ? P[prev][u] * y[u + 1][v + 1] : fma(P[prev][u], y[u + 1][v + 1], acc);
+          first = false;
+        }
+        P[mask][v] = acc;
+      }
+    }
+  }
+  T total = P[FULL][0] * y[1][0];
+#pragma unroll
+  for (int v = 1; v < K; ++v) total = fma(P[FULL][v], y[v + 1][0], total);
+  return T(0.5) * total;
 }
 
 // ---------------------------------------------------------------------------
