@@ -69,6 +69,14 @@ def lib():
                                        c_i64, dp, ctypes.c_void_p]
     L.orc_estimate_plain.argtypes = [ctypes.c_void_p, c_i64]
     L.orc_combine.argtypes = [c_int, dp, dp, dp, dp, dp]
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    L.orc_cube_max.argtypes = [c_int, c_int, c_int, dp, c_int, dp, c_int, c_i64, c_u64, c_u32, dp]
+    L.orc_spring_envelope.argtypes = [c_i64, dp, u64p, dp]
+    L.orc_spring_pick.argtypes = [c_i64, u64p, c_u64]
+    L.orc_spring_pick.restype = c_i64
+    L.orc_spring_trials.argtypes = [c_int, c_int, c_int, dp, c_int, dp, c_int, u64p, c_d, c_u64, c_u32, c_u64,
+                                    c_i64, i64p, dp, dp, dp, dp, i32p]
     _lib = L
     return L
 
@@ -316,6 +324,56 @@ def combine(I, var):
     return Ib.value, sb.value, chi.value
 
 
+# ------------------------------------------------------------ SPRING
+def cube_max(integrand_id, edges, theta, ncall, seed, it, ng, wmax=None):
+    """Fold the largest weight of each of the ng^d cubes of one stratified
+    iteration into wmax (new zero array when None)."""
+    e = _d(edges)
+    d, n1 = e.shape
+    th = _d(theta)
+    out = np.zeros(ng ** d) if wmax is None else wmax
+    assert out.dtype == np.float64 and out.flags.c_contiguous and out.size == ng ** d
+    _check(lib().orc_cube_max(integrand_id, d, n1 - 1, _ptr(e, ctypes.c_double), ng, _ptr(th, ctypes.c_double),
+                              th.size, int(ncall), int(seed), int(it), _ptr(out, ctypes.c_double)), "orc_cube_max")
+    return out
+
+
+def spring_envelope(wmax):
+    """Integer envelope q (quanta of unit = max(wmax) / 2^20 per cube)."""
+    w = _d(wmax)
+    q = np.zeros(w.size, np.uint64)
+    unit = ctypes.c_double()
+    _check(lib().orc_spring_envelope(w.size, _ptr(w, ctypes.c_double), _ptr(q, ctypes.c_uint64),
+                                     ctypes.byref(unit)), "orc_spring_envelope")
+    return q, unit.value
+
+
+def spring_pick(q, r64):
+    """Cube chosen by the 64-bit integer r64 under envelope q."""
+    qa = np.ascontiguousarray(q, dtype=np.uint64)
+    P = np.zeros(qa.size + 1, np.uint64)
+    P[1:] = np.cumsum(qa, dtype=np.uint64)
+    return int(lib().orc_spring_pick(qa.size, _ptr(P, ctypes.c_uint64), int(r64)))
+
+
+def spring_trials(integrand_id, edges, theta, ng, q, unit, seed, pass_, trial0, ntrials):
+    """Per-trial record of SPRING trials trial0 .. trial0+ntrials-1."""
+    e = _d(edges)
+    d, n1 = e.shape
+    th = _d(theta)
+    qa = np.ascontiguousarray(q, dtype=np.uint64)
+    out = dict(cube=np.zeros(ntrials, np.int64), x=np.zeros((ntrials, d)), w=np.zeros(ntrials),
+               env=np.zeros(ntrials), u=np.zeros(ntrials), kept=np.zeros(ntrials, np.int32))
+    _check(lib().orc_spring_trials(integrand_id, d, n1 - 1, _ptr(e, ctypes.c_double), ng, _ptr(th, ctypes.c_double),
+                                   th.size, _ptr(qa, ctypes.c_uint64), float(unit), int(seed), int(pass_),
+                                   int(trial0), int(ntrials), _ptr(out["cube"], ctypes.c_int64),
+                                   _ptr(out["x"], ctypes.c_double), _ptr(out["w"], ctypes.c_double),
+                                   _ptr(out["env"], ctypes.c_double), _ptr(out["u"], ctypes.c_double),
+                                   _ptr(out["kept"], ctypes.c_int32)), "orc_spring_trials")
+    out["kept"] = out["kept"].astype(bool)
+    return out
+
+
 # ------------------------------------------------------------ driver
 @dataclass
 class Run:
@@ -326,21 +384,28 @@ class Run:
     chi2dof: float = float("nan")
     edges: np.ndarray | None = None
     n_eff: int = 0
+    wmax: np.ndarray | None = None
 
 
 def integrate(integrand_id, d, nbins, theta, ncall, itmx, seed, alpha=1.5, ng=1, acc=0.0,
-              itmx2=0, edges=None):
+              itmx2=0, edges=None, cube_max_phase2=False):
     """VEGAS (itmx2 == 0) or BASES (itmx grid-optimisation iterations, then
     itmx2 integration iterations with the grid frozen; only the latter are
-    combined).  Paper Sec. 3.1 steps 1-6 and Sec. 6.1 (ITMX, ACC, ITMX1/2)."""
+    combined).  Paper Sec. 3.1 steps 1-6 and Sec. 6.1 (ITMX, ACC, ITMX1/2).
+    cube_max_phase2: also record each cube's largest weight over the
+    integration phase (the input of SPRING) in run.wmax."""
     e = uniform_edges(d, nbins) if edges is None else _d(edges).copy()
     run = Run()
+    if cube_max_phase2:
+        run.wmax = np.zeros(ng ** d)
     it = 0
     phases = [(itmx, True)] + ([(itmx2, False)] if itmx2 else [])
     for nit, adapt in phases:
         Is, vs = [], []
         for _ in range(nit):
             r = iterate(integrand_id, e, theta, ncall, seed, it, ng=ng)
+            if cube_max_phase2 and not adapt:
+                cube_max(integrand_id, e, theta, ncall, seed, it, ng, run.wmax)
             it += 1
             run.n_eff += r["n_eff"]
             Is.append(r["I"])

@@ -564,15 +564,14 @@ static double eval_sample(const problem *pb, uint32_t s, uint32_t *words, int32_
     return fv * J;
 }
 
-static int setup_problem(problem *pb, int id, int d, int nbins, const double *edges, int ng,
-                         const double *theta, int ntheta, int64_t ncall, uint64_t seed,
-                         uint32_t it, uint32_t kid)
+/* The grid, integrand and stream of a problem, without a call count. */
+static int setup_grid_problem(problem *pb, int id, int d, int nbins, const double *edges, int ng,
+                              const double *theta, int ntheta, uint64_t seed, uint32_t it, uint32_t kid)
 {
     if (d < 1 || d > ORC_MAXD) return ORC_E_DIM;
     if (nbins < 2 || nbins > 256) return ORC_E_NBINS;
     int rc = check_integrand(id, d, ntheta);
     if (rc) return rc;
-    if (ncall < 2 || ncall > 4294967296LL) return ORC_E_NCALLS;
     pb->id = id;
     pb->d = d;
     pb->nbins = nbins;
@@ -590,8 +589,18 @@ static int setup_problem(problem *pb, int id, int d, int nbins, const double *ed
             pb->ncubes *= ng;
             if (pb->ncubes > (1LL << 40)) return ORC_E_STRAT;
         }
-        if (ncall / pb->ncubes < 2) return ORC_E_NCALLS;
     }
+    return ORC_OK;
+}
+
+static int setup_problem(problem *pb, int id, int d, int nbins, const double *edges, int ng,
+                         const double *theta, int ntheta, int64_t ncall, uint64_t seed,
+                         uint32_t it, uint32_t kid)
+{
+    int rc = setup_grid_problem(pb, id, d, nbins, edges, ng, theta, ntheta, seed, it, kid);
+    if (rc) return rc;
+    if (ncall < 2 || ncall > 4294967296LL) return ORC_E_NCALLS;
+    if (ng > 1 && ncall / pb->ncubes < 2) return ORC_E_NCALLS;
     return ORC_OK;
 }
 
@@ -732,6 +741,129 @@ int orc_eval_samples(int id, int d, int nbins, const double *edges, int ng,
         if (w) w[i] = wv;
         if (grad && pb.ngrad > 0) memcpy(grad + i * pb.ngrad, gl, pb.ngrad * sizeof(double));
     }
+    return ORC_OK;
+}
+
+/* ===================================================================== */
+/* SPRING: unweighted events from the result of the BASES integration     */
+/* phase (Sec. 3.1; Kawabata, CPC 41 (1986) 127).  Reading used here: the  */
+/* integration phase records the largest weight w = f J seen in each      */
+/* cube; the envelope g_c >= that maximum is constant on cube c.  A trial */
+/* picks a cube with probability proportional to g_c, a point uniform in */
+/* the cube's y-range (mapped through the frozen grid), and keeps it when */
+/* u g_c < w.  Kept points are distributed as w(y) dy, i.e. as f(x) dx,    */
+/* wherever w <= g_c (a trial with w > g_c is kept and counted as an      */
+/* overflow).  The envelope is held as integers, q_c quanta of            */
+/* gmax / 2^20 each, so that the running sums and the cube choice are     */
+/* exact integer arithmetic.                                              */
+/* ===================================================================== */
+#define ORC_SPRING_QSCALE 1048576.0 /* 2^20 quanta at the largest cube maximum */
+#define ORC_SPRING_TAG 2u           /* counter word 1 = group | tag << 8       */
+
+int orc_cube_max(int id, int d, int nbins, const double *edges, int ng, const double *theta, int ntheta,
+                 int64_t ncall, uint64_t seed, uint32_t it, double *wmax)
+{
+    problem pb;
+    if (ng <= 1) return ORC_E_STRAT;
+    int rc = setup_problem(&pb, id, d, nbins, edges, ng, theta, ntheta, ncall, seed, it, 0);
+    if (rc) return rc;
+    int64_t M = pb.ncubes, k = ncall / pb.ncubes;
+    int32_t j[ORC_MAXD];
+    double x[ORC_MAXD], jac;
+    for (int64_t c = 0; c < M; ++c)
+        for (int64_t t = 0; t < k; ++t) {
+            double w = eval_sample(&pb, (uint32_t)(c + t * M), NULL, j, x, &jac, NULL, NULL);
+            if (w > wmax[c]) wmax[c] = w; /* NaN never replaces the maximum */
+        }
+    return ORC_OK;
+}
+
+int orc_spring_envelope(int64_t M, const double *wmax, uint64_t *q, double *unit)
+{
+    if (M < 1) return ORC_E_INVALID;
+    double gmax = 0.0;
+    for (int64_t c = 0; c < M; ++c) {
+        if (wmax[c] > gmax) gmax = wmax[c];
+    }
+    if (!(gmax > 0.0) || isinf(gmax)) return ORC_E_INVALID;
+    for (int64_t c = 0; c < M; ++c)
+        q[c] = wmax[c] > 0.0 ? (uint64_t)ceil((wmax[c] / gmax) * ORC_SPRING_QSCALE) : 0u;
+    *unit = gmax / ORC_SPRING_QSCALE;
+    return ORC_OK;
+}
+
+int64_t orc_spring_pick(int64_t M, const uint64_t *P, uint64_t r64)
+{
+    /* P[0..M] running sums of q; r = floor(r64 T / 2^64) is uniform over
+     * [0, T); the cube is the last c with P[c] <= r */
+    uint64_t T = P[M];
+    uint64_t r = (uint64_t)(((unsigned __int128)r64 * T) >> 64);
+    int64_t lo = 0, hi = M - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) / 2;
+        if (P[mid] <= r)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+int orc_spring_trials(int id, int d, int nbins, const double *edges, int ng, const double *theta, int ntheta,
+                      const uint64_t *q, double unit, uint64_t seed, uint32_t pass, uint64_t trial0,
+                      int64_t ntrials, int64_t *cube, double *x, double *w, double *env, double *u,
+                      int32_t *kept)
+{
+    problem pb;
+    if (ng <= 1) return ORC_E_STRAT;
+    int rc = setup_grid_problem(&pb, id, d, nbins, edges, ng, theta, ntheta, seed, pass, 0);
+    if (rc) return rc;
+    int64_t M = pb.ncubes;
+    if (M > (1LL << 28) || ntrials < 0) return ORC_E_INVALID;
+    uint64_t *P = (uint64_t *)malloc((size_t)(M + 1) * sizeof(uint64_t));
+    if (!P) return ORC_E_INVALID;
+    P[0] = 0;
+    for (int64_t c = 0; c < M; ++c) P[c + 1] = P[c] + q[c];
+    if (P[M] == 0) {
+        free(P);
+        return ORC_E_INVALID;
+    }
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    int nw = d + 3;
+    for (int64_t i = 0; i < ntrials; ++i) {
+        uint64_t t = trial0 + (uint64_t)i;
+        /* words 0..d-1: the point in the cube; d, d+1: the cube choice (low,
+         * high half of a 64-bit integer); d+2: the acceptance uniform */
+        uint32_t words[ORC_MAXD + 4];
+        for (int a = 0; a < nw; a += 4) {
+            uint32_t ctr[4] = {(uint32_t)t, (uint32_t)(a / 4) | (ORC_SPRING_TAG << 8), pass, (uint32_t)(t >> 32)};
+            uint32_t out[4];
+            orc_philox4x32_10(ctr, key, out);
+            for (int b = 0; b < 4 && a + b < nw; ++b) words[a + b] = out[b];
+        }
+        uint64_t r64 = ((uint64_t)words[d + 1] << 32) | words[d];
+        int64_t c = orc_spring_pick(M, P, r64);
+        int32_t j[ORC_MAXD];
+        double delta[ORC_MAXD], xl[ORC_MAXD];
+        int64_t cc = c;
+        for (int a = 0; a < d; ++a) {
+            int jj;
+            orc_bin_strat(words[a], (int)(cc % ng), ng, nbins, &jj, &delta[a]);
+            j[a] = jj;
+            cc /= ng;
+        }
+        double J = orc_map(d, nbins, edges, j, delta, xl);
+        double wv = orc_integrand(id, d, xl, theta, ntheta, NULL) * J;
+        double g = (double)(P[c + 1] - P[c]) * unit;
+        double ua = orc_uniform(words[d + 2]);
+        if (cube) cube[i] = c;
+        if (x) memcpy(x + i * d, xl, (size_t)d * sizeof(double));
+        if (w) w[i] = wv;
+        if (env) env[i] = g;
+        if (u) u[i] = ua;
+        if (kept) kept[i] = (ua * g < wv) ? 1 : 0;
+    }
+    free(P);
     return ORC_OK;
 }
 

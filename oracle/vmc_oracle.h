@@ -135,6 +135,25 @@ int orc_eval_samples(int id, int d, int nbins, const double *edges, int ng,
                      uint32_t *words, int32_t *j, double *x, double *jac, double *f, double *w,
                      double *grad /* [count][ngrad] */);
 
+/* SPRING (unweighted events from the BASES integration phase), see the .c
+ * file for the reading.  Stratified mode only (ng >= 2).
+ *  orc_cube_max: fold the largest w of each cube of one iteration into
+ *    wmax[ng^d] (the caller zeroes it before the first iteration).
+ *  orc_spring_envelope: q[c] = ceil(wmax[c]/gmax 2^20) (0 where wmax <= 0),
+ *    *unit = gmax / 2^20; ORC_E_INVALID when no cube has a positive finite max.
+ *  orc_spring_pick: the cube of a 64-bit random integer, P = running sums of q.
+ *  orc_spring_trials: trials trial0 .. trial0+ntrials-1 of pass `pass`; per
+ *    trial its cube, point x[d], weight w, envelope value g_c, acceptance
+ *    uniform u and whether it is kept (u g_c < w).  Any output may be NULL. */
+int orc_cube_max(int id, int d, int nbins, const double *edges, int ng, const double *theta, int ntheta,
+                 int64_t ncall, uint64_t seed, uint32_t it, double *wmax);
+int orc_spring_envelope(int64_t M, const double *wmax, uint64_t *q, double *unit);
+int64_t orc_spring_pick(int64_t M, const uint64_t *P, uint64_t r64);
+int orc_spring_trials(int id, int d, int nbins, const double *edges, int ng, const double *theta, int ntheta,
+                      const uint64_t *q, double unit, uint64_t seed, uint32_t pass, uint64_t trial0,
+                      int64_t ntrials, int64_t *cube, double *x, double *w, double *env, double *u,
+                      int32_t *kept);
+
 /* Grid refinement of every axis (classic VEGAS), see the .c file. */
 int orc_refine(int d, int nbins, const double *edges_in, const double *b2 /* [d][nbins] */,
                double alpha, double *edges_out);
