@@ -50,6 +50,7 @@ extern "C" {
 #define VMC_E_HIP (-9)       /* a HIP runtime call or launch failed             */
 #define VMC_E_UNBOUND (-10)  /* device buffers not bound with vmc_bind()        */
 #define VMC_E_SCHEDULE (-11) /* schedule values outside their documented range  */
+#define VMC_E_SPRING (-12)   /* SPRING set-up missing or impossible             */
 
 /* --------------------------------------------------------- integrands */
 /* theta is a device array of doubles of the stated length.               */
@@ -103,7 +104,10 @@ int vmc_version(void);
  *   out[0] edges  double[dim][nbins+1]   FP64 bin edges, row per axis
  *   out[1] table  float [dim][nbins][2]  FP32 (lower edge, width) per bin
  *   out[2] bins   double[2][dim][nbins]  plane 0: sum w per bin,
- *                                        plane 1: sum w^2 per bin
+ *                                        plane 1: sum w^2 per bin,
+ *                 followed by a library-private tail (the blocks' partial
+ *                 sums in 32 copies, about 64 x the two planes, and a work
+ *                 counter; zero between calls)
  *   out[3] scal   double[VMC_SCAL_LEN]   scalar block (layout above)
  * Errors: VMC_E_DIM, VMC_E_NBINS. */
 int vmc_workspace_sizes(int dim, int nbins, size_t out[4]);
@@ -119,7 +123,9 @@ int vmc_destroy(vmc_grid_t g);
 
 /* Bind caller-owned device buffers of at least the sizes given by
  * vmc_workspace_sizes().  They must stay allocated while the handle uses
- * them.  Errors: VMC_E_INVALID (NULL handle or pointer). */
+ * them.  The library-private tail of the bins buffer is taken as unknown
+ * and cleared before the next sample pass (vmc_reset clears everything and
+ * sets the uniform grid).  Errors: VMC_E_INVALID (NULL handle or pointer). */
 int vmc_bind(vmc_grid_t g, double *edges, float *table, double *bins, double *scal);
 
 /* Reset to the uniform grid, clear all accumulators and the running
@@ -137,17 +143,32 @@ int bases_stratify(vmc_grid_t g, int ng);
  * map them through the grid, evaluate the integrand with parameters theta
  * (device doubles, ntheta of them), accumulate sum w, sum w^2 and the
  * per-axis per-bin sums (bins buffer), then write I_k and its variance and
- * fold them into the running combination (weights 1/var).  Stream-ordered.
+ * fold them into the running combination (weights 1/var).  Stream-ordered:
+ * the sample kernel (resident blocks pulling tiles of samples) and a small
+ * publish kernel that adds up the blocks' partial sums and writes the bin
+ * sums, the scalar block and the combination.  Calls on one handle must be
+ * ordered on one stream: they share the bound buffers.
  * Errors: VMC_E_UNBOUND, VMC_E_INTEGRAND, VMC_E_PARAMS, VMC_E_NCALLS,
  * VMC_E_DIM (integrand not compiled for this dim), VMC_E_HIP. */
 int vmc_iterate(vmc_grid_t g, int integrand, const double *theta, int ntheta, int64_t ncall,
                 uint64_t seed, uint32_t it, uint32_t flags, void *stream);
 
+/* Per-cube maxima for SPRING (Sec. 3.1: the results of the BASES
+ * integration phase feed event generation).  While a buffer is bound,
+ * every stratified vmc_iterate also folds the largest weight w = f J of
+ * each cube c into cube_max[c] (max with the present value; NaN weights
+ * never win).  The buffer is caller-owned device memory of ncubes >= ng^dim
+ * doubles, zeroed by the caller at the start of the integration phase;
+ * NULL unbinds.  Plain-mode iterations, vmc_iterate_adjoint and
+ * vmc_iterate_fused leave it alone.  Errors: VMC_E_INVALID (also at
+ * iterate time when ncubes < ng^dim). */
+int bases_cube_max(vmc_grid_t g, double *cube_max, int64_t ncubes);
+
 /* Step 5 of Sec. 3.1: re-optimise every axis from the plane-1 bin sums of
  * the last iteration: 3-point smoothing, normalisation, damping
  * ((1-rho)/(-ln rho))^alpha, and rebinning to equal damped weight; writes
- * new FP64 edges and the FP32 table.  An axis whose smoothed sum is zero is
- * left unchanged; alpha = 0 leaves every axis unchanged.
+ * new FP64 edges and the FP32 table.  An axis whose smoothed sum is zero
+ * is left unchanged; alpha = 0 leaves every axis unchanged.
  * Errors: VMC_E_INVALID (alpha < 0 or NaN), VMC_E_UNBOUND, VMC_E_HIP. */
 int vmc_refine(vmc_grid_t g, double alpha, void *stream);
 
@@ -186,8 +207,9 @@ int vmc_dump_samples(vmc_grid_t g, int integrand, const double *theta, int nthet
                      uint64_t seed, uint32_t it, uint32_t flags, int64_t s0, int64_t count,
                      uint32_t *words, void *w, void *f, void *jac, void *stream);
 
-/* Launch shape of the sample kernels.  block_samples: samples (plain) or
- * cube units (stratified) per thread block, a multiple of 256 in
+/* Launch shape of the sample kernels, whose resident blocks pull tiles of
+ * work from a counter.  block_samples: samples (plain) or cube units
+ * (stratified) per tile, a multiple of 256 in
  * [256, 2^24], or 0 for the built-in choice; chunks_per_cube: lanes that
  * share one cube in stratified mode, a power of two in [1, 64], or 0 for
  * the built-in choice.  Errors: VMC_E_SCHEDULE. */
@@ -255,6 +277,60 @@ int vmc_batch_combine_reset(vmc_batch_t b, void *stream);
 
 /* As vmc_timing, for the batched launches of this handle. */
 int vmc_batch_timing(vmc_batch_t b, int enable, double *total_ms, int64_t *launches);
+
+/* ---------------------------------------------------------------- SPRING */
+/* Unweighted event generation from the BASES integration phase (Sec. 3.1;
+ * Kawabata's SPRING).  A trial picks cube c with probability proportional
+ * to its envelope g_c >= the cube's recorded maximum weight, a point
+ * uniform in the cube's y-range mapped through the (frozen) grid, and keeps
+ * the point when u g_c < w = f J.  Kept points are distributed as f(x) dx
+ * where w <= g_c; trials with w > g_c are kept and counted as overflows.
+ * The envelope is integer: g_c = q_c gmax/2^20 with q_c = ceil(wmax_c /
+ * gmax 2^20), so the cube choice is exact integer arithmetic.  Trial t of
+ * pass p draws Philox words with counter (t mod 2^32, group | 2 << 8, p,
+ * t div 2^32): words 0..dim-1 place the point, words dim and dim+1 form
+ * the 64-bit cube choice r64 (low, high), word dim+2 the acceptance
+ * uniform.  The grid must be stratified (ng >= 2, ng^dim <= 2^28).
+ *
+ * State buffer (8-byte slots): 0 one quantum (double), 1 gmax (double),
+ * 2 T = sum q_c, 3 envelope integral T quantum / ng^dim (double; the
+ * keep rate is about I / this), 4 log2 of the guide size, 5 ng^dim,
+ * 8 trials run, 9 trials kept, 10 overflows, 11 next event slot. */
+#define VMC_SP_UNIT 0
+#define VMC_SP_GMAX 1
+#define VMC_SP_TOTAL 2
+#define VMC_SP_ENV 3
+#define VMC_SP_TRIALS 8
+#define VMC_SP_KEPT 9
+#define VMC_SP_OVER 10
+#define VMC_SP_SLOT 11
+
+/* Bytes of the SPRING buffers of a stratified grid: out[0] running sums
+ * uint64[ng^dim + 1], out[1] guide table uint32[K+1] (K the smallest power
+ * of two >= ng^dim), out[2] state.  Errors: VMC_E_STRAT. */
+int spring_workspace_sizes(vmc_grid_t g, size_t out[3]);
+
+/* Build the envelope from cube_max (ng^dim doubles, e.g. filled through
+ * bases_cube_max): zeroes the state's counters.  Synchronous on `stream`.
+ * Errors: VMC_E_STRAT, VMC_E_INVALID, VMC_E_SPRING (a +Inf maximum, or no
+ * positive one), VMC_E_HIP. */
+int spring_setup(vmc_grid_t g, const double *cube_max, uint64_t *prefix, uint32_t *guide, uint64_t *state,
+                 void *stream);
+
+/* Zero the trial, keep, overflow and slot counters (stream-ordered). */
+int spring_clear_counts(uint64_t *state, void *stream);
+
+/* Run trials trial0 .. trial0+ntrials-1 of pass `pass` with the buffers of
+ * the last spring_setup on this handle (same stratification).  Kept points
+ * are appended at the state's slot counter: events[slot][dim] (float, or
+ * double with VMC_FLAG_FP64) and event_trial[slot] (may be NULL) for slots
+ * below max_events; the order of slots within a call is not specified,
+ * event_trial identifies each event.  Stream-ordered.  Errors: as
+ * vmc_iterate, VMC_E_SPRING (buffers not set up), VMC_E_INVALID. */
+int spring_generate(vmc_grid_t g, int integrand, const double *theta, int ntheta, const uint64_t *prefix,
+                    const uint32_t *guide, uint64_t *state, uint64_t seed, uint32_t pass, int64_t trial0,
+                    int64_t ntrials, int64_t max_events, void *events, uint64_t *event_trial, uint32_t flags,
+                    void *stream);
 
 #ifdef __cplusplus
 }

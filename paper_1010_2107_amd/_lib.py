@@ -19,11 +19,13 @@ FLAG_FP64 = 1
 
 S_S1, S_S2, S_V, S_NONFINITE, S_I, S_VAR, S_NEFF, S_NZERO = 0, 1, 2, 3, 4, 5, 6, 7
 S_NITER, S_IBAR, S_SIGBAR, S_CHI2, S_GRAD, SCAL_LEN = 11, 14, 15, 16, 32, 128
+SP_UNIT, SP_GMAX, SP_TOTAL, SP_ENV, SP_KBITS, SP_NCUBES = 0, 1, 2, 3, 4, 5
+SP_TRIALS, SP_KEPT, SP_OVER, SP_SLOT = 8, 9, 10, 11
 
 ERRORS = {
     -1: "VMC_E_INVALID", -2: "VMC_E_DIM", -3: "VMC_E_NBINS", -4: "VMC_E_NCALLS", -5: "VMC_E_INTEGRAND",
     -6: "VMC_E_PARAMS", -7: "VMC_E_STRAT", -8: "VMC_E_GRID", -9: "VMC_E_HIP", -10: "VMC_E_UNBOUND",
-    -11: "VMC_E_SCHEDULE",
+    -11: "VMC_E_SCHEDULE", -12: "VMC_E_SPRING",
 }
 
 
@@ -75,6 +77,12 @@ _SIGS = {
     "vmc_refine_batched": (_c.c_int, [_vp, _c.c_double, _vp]),
     "vmc_batch_combine_reset": (_c.c_int, [_vp, _vp]),
     "vmc_batch_timing": (_c.c_int, [_vp, _c.c_int, _c.POINTER(_c.c_double), _c.POINTER(_c.c_int64)]),
+    "bases_cube_max": (_c.c_int, [_vp, _vp, _c.c_int64]),
+    "spring_workspace_sizes": (_c.c_int, [_vp, _c.POINTER(_c.c_size_t)]),
+    "spring_setup": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "spring_clear_counts": (_c.c_int, [_vp, _vp]),
+    "spring_generate": (_c.c_int, [_vp, _c.c_int, _vp, _c.c_int, _vp, _vp, _vp, _c.c_uint64, _c.c_uint32,
+                                   _c.c_int64, _c.c_int64, _c.c_int64, _vp, _vp, _c.c_uint32, _vp]),
 }
 
 

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -16,6 +17,7 @@
 #include "vmc_error.hpp"
 #include "vmc_registry.hpp"
 #include "vmc_small.hpp"
+#include "vmc_spring_setup.hpp"
 
 using namespace vmc;
 
@@ -55,6 +57,17 @@ struct vmc_grid_s {
   double* scal = nullptr;
   int block_items = 0;  // 0: built-in
   int chunks = 0;       // 0: built-in
+  // The partial-sum copies and the work counter behind the bin sums may be
+  // non-zero (buffers bound and not reset yet): cleared before a pass.
+  bool acc_dirty = true;
+  // per-cube maxima of stratified forward passes (SPRING input), or NULL
+  double* cube_max = nullptr;
+  int64_t cube_max_n = 0;
+  // buffers of the last successful spring_setup and the stratification they hold
+  const uint64_t* sp_prefix = nullptr;
+  const uint32_t* sp_guide = nullptr;
+  const uint64_t* sp_state = nullptr;
+  int sp_ng = 0;
   bool timing = false;  // record events around every sample-kernel launch
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used = 0;
@@ -66,6 +79,12 @@ struct vmc_grid_s {
     }
   }
 };
+
+// The bins buffer: the published [2][d][N] sums, then kStripes copies of
+// the block partial sums (2 d N bins and kStripeScal scalars each, padded
+// to 128 bytes).
+static size_t stripe_len(int d, int N) { return (static_cast<size_t>(2) * d * N + kStripeScal + 15) / 16 * 16; }
+static size_t bins_total(int d, int N) { return static_cast<size_t>(2) * d * N + kStripes * stripe_len(d, N); }
 
 extern "C" {
 
@@ -79,7 +98,7 @@ int vmc_workspace_sizes(int dim, int nbins, size_t out[4]) {
   if (nbins < 2 || nbins > 256) return fail(VMC_E_NBINS, "nbins %d outside [2,256]", nbins);
   out[0] = sizeof(double) * static_cast<size_t>(dim) * (nbins + 1);
   out[1] = sizeof(float) * 2 * static_cast<size_t>(dim) * nbins;
-  out[2] = sizeof(double) * 2 * static_cast<size_t>(dim) * nbins;
+  out[2] = sizeof(double) * bins_total(dim, nbins);
   out[3] = sizeof(double) * S_LEN;
   return VMC_OK;
 }
@@ -108,6 +127,7 @@ int vmc_bind(vmc_grid_t g, double* edges, float* table, double* bins, double* sc
   g->table = table;
   g->bins = bins;
   g->scal = scal;
+  g->acc_dirty = true;
   return VMC_OK;
 }
 
@@ -121,8 +141,9 @@ int vmc_reset(vmc_grid_t g, void* stream) {
   int rc = need_bound(g);
   if (rc) return rc;
   hipLaunchKernelGGL(k_reset, dim3(16), dim3(kBlock), 0, static_cast<hipStream_t>(stream), g->edges, g->table,
-                     g->bins, g->scal, g->d, g->N);
+                     g->bins, static_cast<int>(bins_total(g->d, g->N)), g->scal, g->d, g->N);
   HIP_TRY(hipGetLastError(), "k_reset launch");
+  g->acc_dirty = false;
   return VMC_OK;
 }
 
@@ -135,6 +156,14 @@ int bases_stratify(vmc_grid_t g, int ng) {
   double cubes = std::pow(static_cast<double>(ng), g->d);
   if (cubes > 1099511627776.0) return fail(VMC_E_STRAT, "ng^dim = %.3g exceeds 2^40", cubes);
   g->ng = ng;
+  return VMC_OK;
+}
+
+int bases_cube_max(vmc_grid_t g, double* cube_max, int64_t ncubes) {
+  if (!g) return fail(VMC_E_INVALID, "grid handle is NULL");
+  if (cube_max && ncubes < 1) return fail(VMC_E_INVALID, "ncubes %lld < 1", (long long)ncubes);
+  g->cube_max = cube_max;
+  g->cube_max_n = cube_max ? ncubes : 0;
   return VMC_OK;
 }
 
@@ -163,7 +192,6 @@ struct Plan {
   SampleArgs A{};
   bool strat = false;
   uint64_t items = 0;  // samples or cube units
-  uint64_t grid = 0;
   size_t lds = 0;
   int d = 0;
   double n_eff = 0;
@@ -188,6 +216,8 @@ int plan_launch(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
   A.table32 = g->table;
   A.edges = g->edges;
   A.bins = g->bins;
+  A.stripes = g->bins + static_cast<size_t>(2) * g->d * g->N;
+  A.stripe_len = static_cast<uint32_t>(stripe_len(g->d, g->N));
   A.scal = g->scal;
   A.theta = theta;
   A.key = Key{static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32)};
@@ -200,16 +230,7 @@ int plan_launch(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
     A.ncall = static_cast<uint64_t>(ncall);
     P.items = A.ncall;
     P.n_eff = static_cast<double>(ncall);
-    // built-in: at least 1024 blocks, at most 8192 samples per block (many
-    // short blocks even out the per-block variation of cut-dependent work
-    // and the tail of the last wave of blocks)
-    uint64_t b = g->block_items;
-    if (!b) {
-      b = (A.ncall + 1023) / 1024;
-      b = ((b + kBlock - 1) / kBlock) * kBlock;
-      b = std::min<uint64_t>(std::max<uint64_t>(b, kBlock), 8192);
-    }
-    A.block_items = b;
+    A.block_items = g->block_items;  // 0: chosen at launch
   } else {
     uint64_t M = 1;
     for (int a = 0; a < g->d; ++a) M *= static_cast<uint64_t>(g->ng);
@@ -234,21 +255,48 @@ int plan_launch(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
     while ((1u << lg) < G) ++lg;
     A.log2G = lg;
     P.items = M << lg;
-    uint64_t b = g->block_items;
-    if (!b) {
-      b = (P.items + 511) / 512;
-      b = ((b + kBlock - 1) / kBlock) * kBlock;
-      if (b < kBlock) b = kBlock;
-    }
-    A.block_items = b;
+    A.block_items = g->block_items;  // 0: chosen at launch
   }
-  P.grid = (P.items + A.block_items - 1) / A.block_items;
-  if (P.grid > 0x7fffffffULL) return fail(VMC_E_SCHEDULE, "grid of %llu blocks too large", (unsigned long long)P.grid);
   P.d = g->d;
   P.lds = static_cast<size_t>(P.ks->tab_entry_bytes) * g->d * g->N;
   return VMC_OK;
 }
 
+// Blocks of one kernel that fit on the current device at once (cached per
+// device, kernel and LDS size).
+struct OccEntry {
+  int dev;
+  const void* fn;
+  size_t lds;
+  int blocks;
+};
+std::mutex g_occ_mu;
+std::vector<OccEntry> g_occ;
+
+int resident_blocks(const void* fn, size_t lds, int* out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  {
+    std::lock_guard<std::mutex> lk(g_occ_mu);
+    for (const auto& e : g_occ)
+      if (e.dev == dev && e.fn == fn && e.lds == lds) {
+        *out = e.blocks;
+        return VMC_OK;
+      }
+  }
+  int per_cu = 0, cus = 0;
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, lds), "occupancy query");
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count query");
+  const int blocks = std::max(1, per_cu) * std::max(1, cus);
+  std::lock_guard<std::mutex> lk(g_occ_mu);
+  g_occ.push_back(OccEntry{dev, fn, lds, blocks});
+  *out = blocks;
+  return VMC_OK;
+}
+
+// One sample pass: blocks add their partial sums into kStripes copies; the
+// publish kernel then adds the copies up and forms the estimate.  The
+// copies are zero between passes (cleared here after a bind).
 int launch_sample(vmc_grid_t g, const Plan& P, int kind, hipStream_t stream) {
   const void* fn = P.strat ? P.ks->strat[kind] : P.ks->plain[kind];
   if (!fn) return fail(VMC_E_INTEGRAND, "integrand has no parameters to differentiate");
@@ -260,6 +308,27 @@ int launch_sample(vmc_grid_t g, const Plan& P, int kind, hipStream_t stream) {
                                      hipGetErrorString(e));
   }
   SampleArgs A = P.A;
+  if (!A.block_items) {
+    // built-in: one tile per block; plain: at least 1024 blocks, at most
+    // 8192 samples per block (short blocks even out the cut-dependent cost
+    // and the tail of the last wave); stratified: about 512 blocks
+    uint64_t b = P.strat ? (P.items + 511) / 512 : (P.items + 1023) / 1024;
+    b = ((b + kBlock - 1) / kBlock) * kBlock;
+    b = std::max<uint64_t>(b, kBlock);
+    if (!P.strat) b = std::min<uint64_t>(b, 8192);
+    A.block_items = b;
+  }
+  A.ntiles = (P.items + A.block_items - 1) / A.block_items;
+  if (A.ntiles > 0x7fffffffULL) return fail(VMC_E_SCHEDULE, "%llu tiles: too many", (unsigned long long)A.ntiles);
+  const uint64_t grid = A.ntiles;
+  const int nb = 2 * g->d * g->N;
+  if (g->acc_dirty) {
+    const int n = static_cast<int>(bins_total(g->d, g->N)) - nb;
+    hipLaunchKernelGGL(k_clear, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, P.A.stripes, n, g->scal,
+                       0, 0);
+    HIP_TRY(hipGetLastError(), "k_clear launch");
+    g->acc_dirty = false;
+  }
   void* args[] = {&A};
   std::pair<hipEvent_t, hipEvent_t>* ev = nullptr;
   if (g->timing) {
@@ -272,9 +341,15 @@ int launch_sample(vmc_grid_t g, const Plan& P, int kind, hipStream_t stream) {
     ev = &g->events[g->events_used++];
     HIP_TRY(hipEventRecord(ev->first, stream), "hipEventRecord");
   }
-  HIP_TRY(hipLaunchKernel(fn, dim3(static_cast<unsigned>(P.grid)), dim3(kBlock), args, lds, stream),
+  HIP_TRY(hipLaunchKernel(fn, dim3(static_cast<unsigned>(grid)), dim3(kBlock), args, lds, stream),
           "sample kernel launch");
   if (ev) HIP_TRY(hipEventRecord(ev->second, stream), "hipEventRecord");
+  const int pub_blocks = std::max(1, (nb + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_publish, dim3(pub_blocks), dim3(kBlock), 0, stream, g->bins, P.A.stripes,
+                     static_cast<int>(P.A.stripe_len), nb, g->scal, (kind & KIND_FWD) ? 1 : 0,
+                     P.strat ? 1 : 0, (kind & KIND_ADJ) ? P.ks->ngrad : 0, P.n_eff, static_cast<double>(P.A.k),
+                     static_cast<double>(P.A.M));
+  HIP_TRY(hipGetLastError(), "k_publish launch");
   return VMC_OK;
 }
 
@@ -287,17 +362,15 @@ int vmc_iterate(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
   Plan P;
   int rc = plan_launch(g, integrand, theta, ntheta, ncall, seed, it, flags, P);
   if (rc) return rc;
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const int nb = 2 * g->d * g->N;
-  hipLaunchKernelGGL(k_clear, dim3((nb + kBlock - 1) / kBlock), dim3(kBlock), 0, st, g->bins, nb, g->scal, 0,
-                     S_NZERO + 1);
-  HIP_TRY(hipGetLastError(), "k_clear launch");
-  rc = launch_sample(g, P, KIND_FWD, st);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, g->scal, P.strat ? 1 : 0, P.n_eff,
-                     static_cast<double>(P.A.k), static_cast<double>(P.A.M), 1, 0);
-  HIP_TRY(hipGetLastError(), "k_finalize launch");
-  return VMC_OK;
+  int kind = KIND_FWD;
+  if (P.strat && g->cube_max) {
+    if (static_cast<uint64_t>(g->cube_max_n) < P.A.M)
+      return fail(VMC_E_INVALID, "cube-maximum buffer holds %lld cubes, the stratification has %u",
+                  (long long)g->cube_max_n, P.A.M);
+    P.A.cube_max = g->cube_max;
+    kind |= KIND_CMAX;
+  }
+  return launch_sample(g, P, kind, static_cast<hipStream_t>(stream));
 }
 
 int vmc_iterate_adjoint(vmc_grid_t g, int integrand, const double* theta, int ntheta, int64_t ncall,
@@ -306,16 +379,7 @@ int vmc_iterate_adjoint(vmc_grid_t g, int integrand, const double* theta, int nt
   int rc = plan_launch(g, integrand, theta, ntheta, ncall, seed, it, flags, P);
   if (rc) return rc;
   if (P.ks->ngrad <= 0) return fail(VMC_E_INTEGRAND, "integrand %d has no parameters to differentiate", integrand);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(k_clear, dim3(1), dim3(kBlock), 0, st, g->bins, 0, g->scal, S_GRAD,
-                     S_GRAD + 5 * P.ks->ngrad);
-  HIP_TRY(hipGetLastError(), "k_clear launch");
-  rc = launch_sample(g, P, KIND_ADJ, st);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, g->scal, P.strat ? 1 : 0, P.n_eff,
-                     static_cast<double>(P.A.k), static_cast<double>(P.A.M), 0, P.ks->ngrad);
-  HIP_TRY(hipGetLastError(), "k_finalize launch");
-  return VMC_OK;
+  return launch_sample(g, P, KIND_ADJ, static_cast<hipStream_t>(stream));
 }
 
 int vmc_iterate_fused(vmc_grid_t g, int integrand, const double* theta, int ntheta, int64_t ncall, uint64_t seed,
@@ -324,20 +388,7 @@ int vmc_iterate_fused(vmc_grid_t g, int integrand, const double* theta, int nthe
   int rc = plan_launch(g, integrand, theta, ntheta, ncall, seed, it, flags, P);
   if (rc) return rc;
   if (P.ks->ngrad <= 0) return fail(VMC_E_INTEGRAND, "integrand %d has no parameters to differentiate", integrand);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const int nb = 2 * g->d * g->N;
-  hipLaunchKernelGGL(k_clear, dim3((nb + kBlock - 1) / kBlock), dim3(kBlock), 0, st, g->bins, nb, g->scal, 0,
-                     S_NZERO + 1);
-  HIP_TRY(hipGetLastError(), "k_clear launch");
-  hipLaunchKernelGGL(k_clear, dim3(1), dim3(kBlock), 0, st, g->bins, 0, g->scal, S_GRAD,
-                     S_GRAD + 5 * P.ks->ngrad);
-  HIP_TRY(hipGetLastError(), "k_clear launch");
-  rc = launch_sample(g, P, KIND_FUSED, st);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, st, g->scal, P.strat ? 1 : 0, P.n_eff,
-                     static_cast<double>(P.A.k), static_cast<double>(P.A.M), 1, P.ks->ngrad);
-  HIP_TRY(hipGetLastError(), "k_finalize launch");
-  return VMC_OK;
+  return launch_sample(g, P, KIND_FUSED, static_cast<hipStream_t>(stream));
 }
 
 int vmc_timing(vmc_grid_t g, int enable, double* total_ms, int64_t* launches) {
@@ -430,6 +481,151 @@ int vmc_dump_samples(vmc_grid_t g, int integrand, const double* theta, int nthet
   HIP_TRY(hipLaunchKernel(P.ks->dump, dim3(static_cast<unsigned>(grid)), dim3(kBlock), args, P.lds,
                           static_cast<hipStream_t>(stream)),
           "dump kernel launch");
+  return VMC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// SPRING
+// ---------------------------------------------------------------------------
+namespace {
+
+struct SpringShape {
+  uint64_t M = 0, K = 0, nblk = 0;
+  uint32_t kbits = 0;
+};
+
+int spring_shape(vmc_grid_t g, SpringShape& S) {
+  if (!g) return fail(VMC_E_INVALID, "grid handle is NULL");
+  if (g->ng <= 1) return fail(VMC_E_STRAT, "SPRING needs a stratified grid (bases_stratify with ng >= 2)");
+  uint64_t M = 1;
+  for (int a = 0; a < g->d; ++a) {
+    M *= static_cast<uint64_t>(g->ng);
+    if (M > (1ull << 28)) return fail(VMC_E_STRAT, "ng^dim exceeds 2^28 cubes for SPRING");
+  }
+  S.M = M;
+  while ((1ull << S.kbits) < M) ++S.kbits;
+  S.K = 1ull << S.kbits;
+  S.nblk = (M + kScanChunk - 1) / kScanChunk;
+  return VMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spring_workspace_sizes(vmc_grid_t g, size_t out[3]) {
+  if (!out) return fail(VMC_E_INVALID, "out is NULL");
+  SpringShape S;
+  int rc = spring_shape(g, S);
+  if (rc) return rc;
+  out[0] = sizeof(uint64_t) * (S.M + 1);
+  out[1] = sizeof(uint32_t) * (S.K + 1);
+  out[2] = sizeof(uint64_t) * (SP_HDR + S.nblk);
+  return VMC_OK;
+}
+
+int spring_setup(vmc_grid_t g, const double* cube_max, uint64_t* prefix, uint32_t* guide, uint64_t* state,
+                 void* stream) {
+  SpringShape S;
+  int rc = spring_shape(g, S);
+  if (rc) return rc;
+  if (!cube_max || !prefix || !guide || !state) return fail(VMC_E_INVALID, "a device buffer is NULL");
+  g->sp_prefix = nullptr;
+  g->sp_guide = nullptr;
+  g->sp_state = nullptr;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const unsigned gblocks = static_cast<unsigned>(std::min<uint64_t>((S.M + kBlock - 1) / kBlock, 2048));
+  hipLaunchKernelGGL(k_sp_init, dim3(1), dim3(64), 0, st, state, S.M, S.kbits);
+  hipLaunchKernelGGL(k_sp_gmax, dim3(gblocks), dim3(kBlock), 0, st, cube_max, S.M, state);
+  hipLaunchKernelGGL(k_sp_blocksum, dim3(static_cast<unsigned>(S.nblk)), dim3(kBlock), 0, st, cube_max, S.M, state);
+  hipLaunchKernelGGL(k_sp_scan_blocks, dim3(1), dim3(kBlock), 0, st, state, S.nblk);
+  hipLaunchKernelGGL(k_sp_scan, dim3(static_cast<unsigned>(S.nblk)), dim3(kBlock), 0, st, cube_max, S.M, state,
+                     prefix);
+  const unsigned kblocks = static_cast<unsigned>(std::min<uint64_t>((S.K + kBlock) / kBlock, 4096));
+  hipLaunchKernelGGL(k_sp_guide, dim3(kblocks), dim3(kBlock), 0, st, prefix, S.M, state, guide);
+  HIP_TRY(hipGetLastError(), "SPRING set-up launch");
+  uint64_t hdr[SP_HDR];
+  HIP_TRY(hipMemcpyAsync(hdr, state, sizeof hdr, hipMemcpyDeviceToHost, st), "SPRING state D2H");
+  HIP_TRY(hipStreamSynchronize(st), "stream synchronize");
+  if (hdr[SP_BADMAX]) return fail(VMC_E_SPRING, "%llu cube maxima are +Inf", (unsigned long long)hdr[SP_BADMAX]);
+  if (hdr[SP_TOTAL] == 0) return fail(VMC_E_SPRING, "no cube has a positive finite maximum weight");
+  g->sp_prefix = prefix;
+  g->sp_guide = guide;
+  g->sp_state = state;
+  g->sp_ng = g->ng;
+  return VMC_OK;
+}
+
+int spring_clear_counts(uint64_t* state, void* stream) {
+  if (!state) return fail(VMC_E_INVALID, "state is NULL");
+  hipLaunchKernelGGL(k_sp_clear_counts, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), state);
+  HIP_TRY(hipGetLastError(), "k_sp_clear_counts launch");
+  return VMC_OK;
+}
+
+int spring_generate(vmc_grid_t g, int integrand, const double* theta, int ntheta, const uint64_t* prefix,
+                    const uint32_t* guide, uint64_t* state, uint64_t seed, uint32_t pass, int64_t trial0,
+                    int64_t ntrials, int64_t max_events, void* events, uint64_t* event_trial, uint32_t flags,
+                    void* stream) {
+  int rc = need_bound(g);
+  if (rc) return rc;
+  SpringShape S;
+  rc = spring_shape(g, S);
+  if (rc) return rc;
+  if (!prefix || prefix != g->sp_prefix || guide != g->sp_guide || state != g->sp_state || g->sp_ng != g->ng)
+    return fail(VMC_E_SPRING, "these buffers have not been set up by spring_setup for this stratification");
+  if (integrand < VMC_CONST || integrand > VMC_PSVOL) return fail(VMC_E_INTEGRAND, "unknown integrand id %d", integrand);
+  const bool fp64 = flags & VMC_FLAG_FP64;
+  const KernelSet* ks = lookup_kernels(integrand, g->d, fp64);
+  if (!ks)
+    return fail(VMC_E_DIM, "integrand %d is not compiled for dim %d (%s)", integrand, g->d, fp64 ? "fp64" : "fp32");
+  if (ntheta != ks->ntheta)
+    return fail(VMC_E_PARAMS, "integrand %d in dim %d takes %d parameters, got %d", integrand, g->d, ks->ntheta,
+                ntheta);
+  if (ntheta > 0 && !theta) return fail(VMC_E_INVALID, "theta is NULL");
+  if (trial0 < 0 || ntrials < 0 || ntrials > (1ll << 40) || trial0 > (1ll << 62))
+    return fail(VMC_E_INVALID, "trials [%lld, +%lld): need trial0 in [0, 2^62] and ntrials in [0, 2^40]",
+                (long long)trial0, (long long)ntrials);
+  if (max_events < 0 || (max_events > 0 && !events))
+    return fail(VMC_E_INVALID, "max_events %lld needs an event buffer", (long long)max_events);
+  if (ntrials == 0) return VMC_OK;
+  SpringArgs SP{};
+  SampleArgs& A = SP.A;
+  A.table32 = g->table;
+  A.edges = g->edges;
+  A.bins = g->bins;
+  A.scal = g->scal;
+  A.theta = theta;
+  A.key = Key{static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32)};
+  A.it = pass;
+  A.nbins = static_cast<uint32_t>(g->N);
+  A.ng = static_cast<uint32_t>(g->ng);
+  A.per_cube = (g->N % g->ng == 0) ? static_cast<uint32_t>(g->N / g->ng) : 0u;
+  A.M = static_cast<uint32_t>(S.M);
+  SP.prefix = prefix;
+  SP.guide = guide;
+  SP.state = state;
+  SP.trial0 = static_cast<uint64_t>(trial0);
+  SP.ntrials = static_cast<uint64_t>(ntrials);
+  SP.max_events = static_cast<uint64_t>(max_events);
+  SP.events = events;
+  SP.event_trial = event_trial;
+  const size_t lds = static_cast<size_t>(ks->tab_entry_bytes) * g->d * g->N;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(ks->spring, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return fail(VMC_E_NBINS, "dim x nbins needs %zu bytes of LDS per block: %s", lds,
+                                     hipGetErrorString(e));
+  }
+  int resident = 0;
+  rc = resident_blocks(ks->spring, lds, &resident);
+  if (rc) return rc;
+  const uint64_t grid = std::min<uint64_t>((SP.ntrials + kBlock - 1) / kBlock, static_cast<uint64_t>(resident));
+  void* args[] = {&SP};
+  HIP_TRY(hipLaunchKernel(ks->spring, dim3(static_cast<unsigned>(grid)), dim3(kBlock), args, lds,
+                          static_cast<hipStream_t>(stream)),
+          "SPRING kernel launch");
   return VMC_OK;
 }
 

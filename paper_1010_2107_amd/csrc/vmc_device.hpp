@@ -45,9 +45,7 @@ __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, 
   out[3] = c3;
 }
 
-// The D words of sample s: word a is word a%4 of the block with counter
-// (s, a/4, it, kid).  The first round multiplies only c0 = s and c2 = it,
-// which all word groups share, so its products are formed once.
+// Rounds 2-10 of Philox4x32-10 given the first round's products.
 __device__ __forceinline__ void philox10_from_round1(uint32_t hi0, uint32_t lo0, uint32_t hi1, uint32_t lo1,
                                                      uint32_t c1, uint32_t c3, Key key, uint32_t (&out)[4]) {
   uint32_t k0 = key.k0, k1 = key.k1;
@@ -74,21 +72,32 @@ __device__ __forceinline__ void philox10_from_round1(uint32_t hi0, uint32_t lo0,
   out[3] = c3;
 }
 
-template <int D>
-__device__ __forceinline__ void sample_words(uint32_t s, uint32_t it, uint32_t kid, Key key,
-                                             uint32_t (&w)[D]) {
-  const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * s;
-  const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * it;
+// NW words of the block sequence with counter (c0, g | tag, c2, c3),
+// g = 0, 1, ...: word i is word i%4 of block g = i/4.  The first round
+// multiplies only c0 and c2, which all blocks share, so its products are
+// formed once.
+template <int NW>
+__device__ __forceinline__ void philox_words(uint32_t c0, uint32_t tag, uint32_t c2, uint32_t c3, Key key,
+                                             uint32_t (&w)[NW]) {
+  const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
+  const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
   const uint32_t hi0 = static_cast<uint32_t>(pa >> 32), lo0 = static_cast<uint32_t>(pa);
   const uint32_t hi1 = static_cast<uint32_t>(pb >> 32), lo1 = static_cast<uint32_t>(pb);
 #pragma unroll
-  for (int g = 0; g < (D + 3) / 4; ++g) {
+  for (int g = 0; g < (NW + 3) / 4; ++g) {
     uint32_t blk[4];
-    philox10_from_round1(hi0, lo0, hi1, lo1, static_cast<uint32_t>(g), kid, key, blk);
+    philox10_from_round1(hi0, lo0, hi1, lo1, static_cast<uint32_t>(g) | tag, c3, key, blk);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      if (4 * g + q < D) w[4 * g + q] = blk[q];
+      if (4 * g + q < NW) w[4 * g + q] = blk[q];
   }
+}
+
+// The D words of sample s of iteration it (stream tag 0).
+template <int D>
+__device__ __forceinline__ void sample_words(uint32_t s, uint32_t it, uint32_t kid, Key key,
+                                             uint32_t (&w)[D]) {
+  philox_words<D>(s, 0u, it, kid, key, w);
 }
 
 // ---------------------------------------------------------------------------

@@ -39,7 +39,19 @@ enum : int {
   S_LEN = 128
 };
 
-enum : int { KIND_FWD = 1, KIND_ADJ = 2, KIND_FUSED = 3 };
+// Block partial sums go to one of kStripes copies (block b to copy b mod
+// kStripes) so that no address sees more than 1/kStripes of the blocks'
+// atomics; the publish kernel adds the copies up.  A copy holds the 2 D N
+// bin sums and then kStripeScal scalar slots: S1, S2, non-finite count,
+// zero count, V, then per gradient parameter its sum, sum of squares and
+// V_p.
+constexpr int kStripes = 32;
+constexpr int kStripeScal = 64;
+enum : int { T_S1 = 0, T_S2 = 1, T_NONFIN = 2, T_NZERO = 3, T_V = 4, T_G = 5 };
+
+// Pass kinds: forward sums, adjoint sums, both; KIND_CMAX (stratified
+// forward only) also folds each cube's largest weight into cube_max.
+enum : int { KIND_FWD = 1, KIND_ADJ = 2, KIND_FUSED = 3, KIND_CMAX = 4 };
 
 // per-thread accumulator slots: S1, S2, non-finite count, zero count, then
 // the gradient sums
@@ -48,8 +60,10 @@ constexpr int kA0 = 4;
 struct SampleArgs {
   const float* table32;  // [d][N][2] (lo, width), FP32
   const double* edges;   // [d][N+1], FP64
-  double* bins;          // [2][d][N]
+  double* bins;          // [2][d][N] published bin sums
+  double* stripes;       // kStripes copies of stripe_len doubles (block partial sums)
   double* scal;          // S_LEN doubles
+  double* cube_max;      // [M] largest weight per cube (KIND_CMAX)
   const double* theta;   // device parameters
   Key key;
   uint32_t it, kid;
@@ -60,8 +74,57 @@ struct SampleArgs {
   uint32_t k;         // samples per cube
   uint32_t log2G;     // lanes per cube = 1 << log2G
   uint64_t ncall;     // plain: samples; stratified: k * M
-  uint64_t block_items;  // samples (plain) or cube units (stratified) per block
+  uint64_t block_items;  // samples (plain) or cube units (stratified) per tile
+  uint64_t ntiles;       // tiles of the launch; block b takes tiles b, b + gridDim.x, ...
+  uint32_t stripe_len;   // doubles per copy: 2 D N bins, then kStripeScal scalars (padded)
 };
+
+// Estimate of one iteration and its variance,
+//   plain:      I = S1/n, var = (S2/n - I^2)/(n-1)
+//   stratified: I = S1/(kM), var = sum_c (k S2_c - S1_c^2)/(k^2 (k-1) M^2),
+// then the running combination with weights 1/var, updated with West's
+// weighted incremental mean so that chi^2 needs no stored history.
+// Iterations with var = 0 are exact; when any exist the combined value is
+// their mean with zero error.
+__device__ inline void finalize_one(double* scal, int strat, double n, double kd, double Md, int fwd, int ngrad) {
+  const double denom = kd * kd * (kd - 1.0) * Md * Md;
+  if (fwd) {
+    const double I = scal[S_S1] / n;
+    const double var = strat ? scal[S_V] / denom : (scal[S_S2] / n - I * I) / (n - 1.0);
+    scal[S_I] = I;
+    scal[S_VAR] = var;
+    scal[S_NEFF] = n;
+    scal[S_NTOTAL] += n;
+    scal[S_NITER] += 1.0;
+    if (var == 0.0) {
+      scal[S_NEXACT] += 1.0;
+      scal[S_SUMEXACT] += I;
+    } else {
+      const double w = 1.0 / var;
+      const double W = scal[S_W] + w;
+      const double delta = I - scal[S_MEAN];
+      const double mean = scal[S_MEAN] + delta * (w / W);
+      scal[S_M2] += w * delta * (I - mean);
+      scal[S_MEAN] = mean;
+      scal[S_W] = W;
+    }
+    if (scal[S_NEXACT] > 0.0) {
+      scal[S_IBAR] = scal[S_SUMEXACT] / scal[S_NEXACT];
+      scal[S_SIGBAR] = 0.0;
+      scal[S_CHI2] = 0.0;
+    } else {
+      scal[S_IBAR] = scal[S_MEAN];
+      scal[S_SIGBAR] = 1.0 / sqrt(scal[S_W]);
+      scal[S_CHI2] = scal[S_NITER] > 1.0 ? scal[S_M2] / (scal[S_NITER] - 1.0) : __builtin_nan("");
+    }
+  }
+  for (int q = 0; q < ngrad; ++q) {
+    double* g = scal + S_GRAD + 5 * q;
+    const double G = g[0] / n;
+    g[3] = G;
+    g[4] = strat ? g[2] / denom : (g[1] / n - G * G) / (n - 1.0);
+  }
+}
 
 // LDS layout: grid table first (16-byte entries for FP64), then histogram.
 template <typename T, int D>
@@ -133,7 +196,23 @@ __device__ __forceinline__ void accumulate(const SampleArgs& A, double* hist, co
   }
 }
 
-// Add the block's accumulators to the scalar block and merge the histogram.
+// The block's copy of the partial sums.
+__device__ __forceinline__ double* block_stripe(const SampleArgs& A) {
+  return A.stripes + static_cast<size_t>(blockIdx.x % kStripes) * A.stripe_len;
+}
+
+// Add the block's histogram to its copy of the bin sums (non-zero bins).
+template <int D>
+__device__ __forceinline__ void flush_hist(const SampleArgs& A, const double* hist) {
+  double* dst = block_stripe(A);
+  const int n = 2 * D * static_cast<int>(A.nbins);
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const double v = hist[i];
+    if (v != 0.0) global_add(&dst[i], v);
+  }
+}
+
+// Add the block's accumulators and histogram to its copy.
 template <class F, int KIND, int NACC>
 __device__ __forceinline__ void flush_block(const SampleArgs& A, double* hist, const double (&acc)[NACC],
                                             double* red) {
@@ -141,23 +220,17 @@ __device__ __forceinline__ void flush_block(const SampleArgs& A, double* hist, c
   constexpr bool HIST = KIND & KIND_FWD, GRAD = KIND & KIND_ADJ;
   constexpr int NG = GRAD ? F::NGRAD : 0;
   int idx[NACC];
-  idx[0] = S_S1;
-  idx[1] = S_S2;
-  idx[2] = S_NONFIN;
-  idx[3] = S_NZERO;
+  idx[0] = T_S1;
+  idx[1] = T_S2;
+  idx[2] = T_NONFIN;
+  idx[3] = T_NZERO;
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
-    idx[kA0 + q] = S_GRAD + 5 * q;
-    idx[kA0 + NG + q] = S_GRAD + 5 * q + 1;
+    idx[kA0 + q] = T_G + q;
+    idx[kA0 + NG + q] = T_G + NG + q;
   }
-  block_sum_to_global<NACC>(acc, red, A.scal, idx);
-  if (HIST) {
-    const int n = 2 * D * static_cast<int>(A.nbins);
-    for (int i = threadIdx.x; i < n; i += kBlock) {
-      const double v = hist[i];
-      if (v != 0.0) global_add(&A.bins[i], v);
-    }
-  }
+  block_sum_to_global<NACC>(acc, red, block_stripe(A) + 2 * D * A.nbins, idx);
+  if (HIST) flush_hist<D>(A, hist);
 }
 
 template <class F, int KIND>
@@ -187,8 +260,9 @@ __device__ __forceinline__ F block_setup(const double* theta) {
 }
 
 // ---------------------------------------------------------------------------
-// Plain (VEGAS) sampling: block b takes samples [b B, (b+1) B), lanes stride
-// through them.
+// Plain (VEGAS) sampling: tile t is samples [t B, (t+1) B), the block's
+// lanes stride through it; by default every block takes one tile and the
+// hardware dispatcher balances the blocks over the CUs.
 // ---------------------------------------------------------------------------
 template <class F, int KIND>
 __global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
@@ -207,18 +281,20 @@ __global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
   for (int i = 0; i < NACC; ++i) acc[i] = 0.0;
   uint32_t cnt[2] = {0u, 0u};  // non-finite and zero weights
 
-  const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * A.block_items;
-  const uint64_t b1 = min(b0 + A.block_items, A.ncall);
   const uint32_t dummy_cc[D] = {};
-  for (uint64_t s = b0 + threadIdx.x; s < b1; s += kBlock) {
-    uint32_t w[D];
-    sample_words<D>(static_cast<uint32_t>(s), A.it, A.kid, A.key, w);
-    int j[D];
-    T x[D], jac;
-    make_point<T, D, false>(A, tab, w, dummy_cc, j, x, jac);
-    T g[F::NGRAD + 1];
-    const T fv = fn.template eval<(KIND & KIND_ADJ) != 0>(x, g);
-    accumulate<F, KIND>(A, hist, j, fv, jac, g, acc, cnt);
+  for (uint64_t t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
+    const uint64_t b0 = t * A.block_items;
+    const uint64_t b1 = min(b0 + A.block_items, A.ncall);
+    for (uint64_t s = b0 + threadIdx.x; s < b1; s += kBlock) {
+      uint32_t w[D];
+      sample_words<D>(static_cast<uint32_t>(s), A.it, A.kid, A.key, w);
+      int j[D];
+      T x[D], jac;
+      make_point<T, D, false>(A, tab, w, dummy_cc, j, x, jac);
+      T g[F::NGRAD + 1];
+      const T fv = fn.template eval<(KIND & KIND_ADJ) != 0>(x, g);
+      accumulate<F, KIND>(A, hist, j, fv, jac, g, acc, cnt);
+    }
   }
   acc[2] = static_cast<double>(cnt[0]);
   acc[3] = static_cast<double>(cnt[1]);
@@ -237,7 +313,7 @@ template <class F, int KIND>
 __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
   using T = typename F::T;
   constexpr int D = F::D;
-  constexpr bool FWD = KIND & KIND_FWD, GRAD = KIND & KIND_ADJ;
+  constexpr bool FWD = KIND & KIND_FWD, GRAD = KIND & KIND_ADJ, CMAX = KIND & KIND_CMAX;
   constexpr int NG = GRAD ? F::NGRAD : 0;
   constexpr int NACC = kA0 + 2 * NG + 1 + NG;  // + V and V_p
   extern __shared__ __align__(16) unsigned char smem[];
@@ -253,9 +329,10 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
 
   const uint32_t G = 1u << A.log2G;
   const uint64_t units = static_cast<uint64_t>(A.M) << A.log2G;
-  const uint64_t u0 = static_cast<uint64_t>(blockIdx.x) * A.block_items;
-  const uint64_t u1 = min(u0 + A.block_items, units);
   const double kd = static_cast<double>(A.k);
+  for (uint64_t tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
+  const uint64_t u0 = tile * A.block_items;
+  const uint64_t u1 = min(u0 + A.block_items, units);
   for (uint64_t base = u0; base < u1; base += kBlock) {
     const uint64_t u = base + threadIdx.x;
     const bool active = u < u1;
@@ -274,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
     const uint32_t t0 = active ? static_cast<uint32_t>((static_cast<uint64_t>(gidx) * A.k) >> A.log2G) : 0u;
     const uint32_t t1 =
         active ? static_cast<uint32_t>((static_cast<uint64_t>(gidx + 1) * A.k) >> A.log2G) : 0u;
-    double c1 = 0.0, c2 = 0.0;
+    double c1 = 0.0, c2 = 0.0, cm = 0.0;
     double cg1[NG + 1], cg2[NG + 1];
 #pragma unroll
     for (int q = 0; q < NG; ++q) cg1[q] = cg2[q] = 0.0;
@@ -292,6 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
         const double wd = static_cast<double>(fv * jac);
         c1 += wd;
         c2 += wd * wd;
+        if (CMAX) cm = fmax(cm, wd);  // a NaN weight never becomes the maximum
       }
 #pragma unroll
       for (int q = 0; q < NG; ++q) {
@@ -305,6 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
         c1 += __shfl_xor(c1, off, kWave);
         c2 += __shfl_xor(c2, off, kWave);
       }
+      if (CMAX) cm = fmax(cm, __shfl_xor(cm, off, kWave));
 #pragma unroll
       for (int q = 0; q < NG; ++q) {
         cg1[q] += __shfl_xor(cg1[q], off, kWave);
@@ -313,34 +392,30 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
     }
     if (active && gidx == 0) {
       if (FWD) acc[kA0 + 2 * NG] += kd * c2 - c1 * c1;
+      if (CMAX && cm > A.cube_max[c]) A.cube_max[c] = cm;  // one writer per cube and launch
 #pragma unroll
       for (int q = 0; q < NG; ++q) acc[kA0 + 1 + 2 * NG + q] += kd * cg2[q] - cg1[q] * cg1[q];
     }
+  }
   }
   acc[2] = static_cast<double>(cnt[0]);
   acc[3] = static_cast<double>(cnt[1]);
   __syncthreads();
   // the V slots go through the same block reduction
   int idx[NACC];
-  idx[0] = S_S1;
-  idx[1] = S_S2;
-  idx[2] = S_NONFIN;
-  idx[3] = S_NZERO;
+  idx[0] = T_S1;
+  idx[1] = T_S2;
+  idx[2] = T_NONFIN;
+  idx[3] = T_NZERO;
 #pragma unroll
   for (int q = 0; q < NG; ++q) {
-    idx[kA0 + q] = S_GRAD + 5 * q;
-    idx[kA0 + NG + q] = S_GRAD + 5 * q + 1;
-    idx[kA0 + 1 + 2 * NG + q] = S_GRAD + 5 * q + 2;
+    idx[kA0 + q] = T_G + q;
+    idx[kA0 + NG + q] = T_G + NG + q;
+    idx[kA0 + 1 + 2 * NG + q] = T_G + 2 * NG + q;
   }
-  idx[kA0 + 2 * NG] = S_V;
-  block_sum_to_global<NACC>(acc, red, A.scal, idx);
-  if (FWD) {
-    const int n = 2 * D * static_cast<int>(A.nbins);
-    for (int i = threadIdx.x; i < n; i += kBlock) {
-      const double v = hist[i];
-      if (v != 0.0) global_add(&A.bins[i], v);
-    }
-  }
+  idx[kA0 + 2 * NG] = T_V;
+  block_sum_to_global<NACC>(acc, red, block_stripe(A) + 2 * D * A.nbins, idx);
+  if (FWD) flush_hist<D>(A, hist);
 }
 
 // ---------------------------------------------------------------------------
@@ -395,34 +470,6 @@ __global__ __launch_bounds__(kBlock) void k_dump(const DumpArgs P) {
   if (P.w) static_cast<T*>(P.w)[i] = fv * jac;
   if (P.f) static_cast<T*>(P.f)[i] = fv;
   if (P.jac) static_cast<T*>(P.jac)[i] = jac;
-}
-
-// Kernel entry points of one integrand instantiation.
-struct KernelSet {
-  const void* plain[4];  // indexed by KIND (1 fwd, 2 adj, 3 fused)
-  const void* strat[4];
-  const void* dump;
-  int ngrad;
-  int ntheta;
-  int tab_entry_bytes;
-};
-
-template <class F>
-KernelSet make_kernel_set() {
-  KernelSet s{};
-  s.plain[KIND_FWD] = reinterpret_cast<const void*>(&k_plain<F, KIND_FWD>);
-  s.strat[KIND_FWD] = reinterpret_cast<const void*>(&k_strat<F, KIND_FWD>);
-  if constexpr (F::NGRAD > 0) {
-    s.plain[KIND_ADJ] = reinterpret_cast<const void*>(&k_plain<F, KIND_ADJ>);
-    s.strat[KIND_ADJ] = reinterpret_cast<const void*>(&k_strat<F, KIND_ADJ>);
-    s.plain[KIND_FUSED] = reinterpret_cast<const void*>(&k_plain<F, KIND_FUSED>);
-    s.strat[KIND_FUSED] = reinterpret_cast<const void*>(&k_strat<F, KIND_FUSED>);
-  }
-  s.dump = reinterpret_cast<const void*>(&k_dump<F>);
-  s.ngrad = F::NGRAD;
-  s.ntheta = F::NTHETA;
-  s.tab_entry_bytes = static_cast<int>(sizeof(typename TabEntry<typename F::T>::type));
-  return s;
 }
 
 }  // namespace vmc

@@ -5,8 +5,40 @@
 #pragma once
 
 #include "vmc_kernels.hpp"
+#include "vmc_spring.hpp"
 
 namespace vmc {
+
+// Kernel entry points of one integrand instantiation.
+struct KernelSet {
+  const void* plain[4];  // indexed by KIND (1 fwd, 2 adj, 3 fused)
+  const void* strat[8];  // and KIND_FWD | KIND_CMAX
+  const void* dump;
+  const void* spring;
+  int ngrad;
+  int ntheta;
+  int tab_entry_bytes;
+};
+
+template <class F>
+KernelSet make_kernel_set() {
+  KernelSet s{};
+  s.plain[KIND_FWD] = reinterpret_cast<const void*>(&k_plain<F, KIND_FWD>);
+  s.strat[KIND_FWD] = reinterpret_cast<const void*>(&k_strat<F, KIND_FWD>);
+  s.strat[KIND_FWD | KIND_CMAX] = reinterpret_cast<const void*>(&k_strat<F, KIND_FWD | KIND_CMAX>);
+  if constexpr (F::NGRAD > 0) {
+    s.plain[KIND_ADJ] = reinterpret_cast<const void*>(&k_plain<F, KIND_ADJ>);
+    s.strat[KIND_ADJ] = reinterpret_cast<const void*>(&k_strat<F, KIND_ADJ>);
+    s.plain[KIND_FUSED] = reinterpret_cast<const void*>(&k_plain<F, KIND_FUSED>);
+    s.strat[KIND_FUSED] = reinterpret_cast<const void*>(&k_strat<F, KIND_FUSED>);
+  }
+  s.dump = reinterpret_cast<const void*>(&k_dump<F>);
+  s.spring = reinterpret_cast<const void*>(&k_spring<F>);
+  s.ngrad = F::NGRAD;
+  s.ntheta = F::NTHETA;
+  s.tab_entry_bytes = static_cast<int>(sizeof(typename TabEntry<typename F::T>::type));
+  return s;
+}
 
 const KernelSet* lookup_gauss_f32(int id, int d);
 const KernelSet* lookup_axes_f32(int id, int d);

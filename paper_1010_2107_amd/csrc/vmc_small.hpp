@@ -1,7 +1,7 @@
 // vmc_small.hpp -- the FP64 kernels around the sample pass: clearing the
-// accumulators, the per-iteration estimate and the running combination of
-// iterations, grid refinement (step 5 of the six-step structure of
-// Kanzaki, arXiv:1010.2107, Sec. 3.1) and the FP32 table build.
+// accumulators, resetting the combination of iterations, grid refinement
+// (step 5 of the six-step structure of Kanzaki, arXiv:1010.2107, Sec. 3.1)
+// and the FP32 table build.
 #pragma once
 
 #include "vmc_kernels.hpp"
@@ -18,55 +18,48 @@ __global__ __launch_bounds__(kBlock) void k_clear(double* bins, int nbins_total,
   for (int i = s_lo + tid; i < s_hi; i += stride) scal[i] = 0.0;
 }
 
-// Estimate of one iteration and its variance,
-//   plain:      I = S1/n, var = (S2/n - I^2)/(n-1)
-//   stratified: I = S1/(kM), var = sum_c (k S2_c - S1_c^2)/(k^2 (k-1) M^2),
-// then the running combination with weights 1/var, updated with West's
-// weighted incremental mean so that chi^2 needs no stored history.
-// Iterations with var = 0 are exact; when any exist the combined value is
-// their mean with zero error.
-__device__ void finalize_one(double* scal, int strat, double n, double kd, double Md, int fwd, int ngrad) {
-  const double denom = kd * kd * (kd - 1.0) * Md * Md;
+// Publish a sample launch: add up the kStripes copies of the partial sums
+// (and clear them), write the bin sums (forward passes), the scalar sums,
+// the estimate and the running combination.
+// Thread i of the grid owns bin i; block 0 also owns the scalar slots.
+__global__ __launch_bounds__(kBlock) void k_publish(double* bins, double* stripes, int stripe_len, int nb,
+                                                    double* scal, int fwd, int strat, int ngrad, double n, double kd,
+                                                    double Md) {
+  __shared__ double tot[kStripeScal];
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < nb) {
+    double v = 0.0;
+    for (int s = 0; s < kStripes; ++s) {
+      double* p = stripes + static_cast<size_t>(s) * stripe_len + i;
+      v += *p;
+      *p = 0.0;
+    }
+    if (fwd) bins[i] = v;
+  }
+  if (blockIdx.x != 0) return;
+  if (threadIdx.x < kStripeScal) {
+    double v = 0.0;
+    for (int s = 0; s < kStripes; ++s) {
+      double* p = stripes + static_cast<size_t>(s) * stripe_len + nb + threadIdx.x;
+      v += *p;
+      *p = 0.0;
+    }
+    tot[threadIdx.x] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   if (fwd) {
-    const double I = scal[S_S1] / n;
-    const double var = strat ? scal[S_V] / denom : (scal[S_S2] / n - I * I) / (n - 1.0);
-    scal[S_I] = I;
-    scal[S_VAR] = var;
-    scal[S_NEFF] = n;
-    scal[S_NTOTAL] += n;
-    scal[S_NITER] += 1.0;
-    if (var == 0.0) {
-      scal[S_NEXACT] += 1.0;
-      scal[S_SUMEXACT] += I;
-    } else {
-      const double w = 1.0 / var;
-      const double W = scal[S_W] + w;
-      const double delta = I - scal[S_MEAN];
-      const double mean = scal[S_MEAN] + delta * (w / W);
-      scal[S_M2] += w * delta * (I - mean);
-      scal[S_MEAN] = mean;
-      scal[S_W] = W;
-    }
-    if (scal[S_NEXACT] > 0.0) {
-      scal[S_IBAR] = scal[S_SUMEXACT] / scal[S_NEXACT];
-      scal[S_SIGBAR] = 0.0;
-      scal[S_CHI2] = 0.0;
-    } else {
-      scal[S_IBAR] = scal[S_MEAN];
-      scal[S_SIGBAR] = 1.0 / sqrt(scal[S_W]);
-      scal[S_CHI2] = scal[S_NITER] > 1.0 ? scal[S_M2] / (scal[S_NITER] - 1.0) : __builtin_nan("");
-    }
+    scal[S_S1] = tot[T_S1];
+    scal[S_S2] = tot[T_S2];
+    scal[S_NONFIN] = tot[T_NONFIN];
+    scal[S_NZERO] = tot[T_NZERO];
+    scal[S_V] = tot[T_V];
   }
   for (int q = 0; q < ngrad; ++q) {
-    double* g = scal + S_GRAD + 5 * q;
-    const double G = g[0] / n;
-    g[3] = G;
-    g[4] = strat ? g[2] / denom : (g[1] / n - G * G) / (n - 1.0);
+    scal[S_GRAD + 5 * q + 0] = tot[T_G + q];
+    scal[S_GRAD + 5 * q + 1] = tot[T_G + ngrad + q];
+    scal[S_GRAD + 5 * q + 2] = tot[T_G + 2 * ngrad + q];
   }
-}
-
-__global__ void k_finalize(double* scal, int strat, double n, double kd, double Md, int fwd, int ngrad) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
   finalize_one(scal, strat, n, kd, Md, fwd, ngrad);
 }
 
@@ -76,8 +69,8 @@ __global__ void k_combine_reset(double* scal) {
 }
 
 // Uniform grid, its table, and cleared accumulators.
-__global__ __launch_bounds__(kBlock) void k_reset(double* edges, float* table, double* bins, double* scal,
-                                                  int d, int N) {
+__global__ __launch_bounds__(kBlock) void k_reset(double* edges, float* table, double* bins, int nbins_total,
+                                                  double* scal, int d, int N) {
   const int tid = blockIdx.x * kBlock + threadIdx.x;
   const int stride = gridDim.x * kBlock;
   for (int i = tid; i < d * (N + 1); i += stride) {
@@ -91,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_reset(double* edges, float* table, d
     table[2 * i] = static_cast<float>(lo);
     table[2 * i + 1] = static_cast<float>(hi - lo);
   }
-  for (int i = tid; i < 2 * d * N; i += stride) bins[i] = 0.0;
+  for (int i = tid; i < nbins_total; i += stride) bins[i] = 0.0;
   for (int i = tid; i < S_LEN; i += stride) scal[i] = 0.0;
 }
 

@@ -29,7 +29,10 @@ class Result:
 
 
 def integrate(integrand, dim, nbins, theta, ncall, itmx, seed, alpha=1.5, ng=1, itmx2=0, acc=0.0, fp64=False,
-              grid: Grid | None = None, it0=0, stream=None) -> Result:
+              grid: Grid | None = None, it0=0, stream=None, cube_max: torch.Tensor | None = None) -> Result:
+    """cube_max (BASES only): a float64 device buffer of ng^dim entries that
+    receives each cube's largest weight over the integration phase, the
+    input of SPRING event generation."""
     g = grid if grid is not None else Grid(dim, nbins)
     assert (g.dim, g.nbins) == (dim, nbins)
     g.reset(stream)
@@ -42,6 +45,9 @@ def integrate(integrand, dim, nbins, theta, ncall, itmx, seed, alpha=1.5, ng=1, 
     for p, (nit, adapt) in enumerate(phases):
         if p > 0:
             g.combine_reset(stream)
+            if cube_max is not None:
+                cube_max.zero_()
+                g.bind_cube_max(cube_max)
         for _ in range(nit):
             g.iterate(integrand, th, ncall, seed, it, fp64=fp64, stream=stream)
             hist[k] = g.scal[L.S_I:L.S_VAR + 1]
@@ -53,6 +59,8 @@ def integrate(integrand, dim, nbins, theta, ncall, itmx, seed, alpha=1.5, ng=1, 
                 r = g.result()
                 if r["Ibar"] != 0 and r["sigbar"] / abs(r["Ibar"]) < acc:
                     break
+    if cube_max is not None:
+        g.bind_cube_max(None)
     r = g.result()
     h = hist[:k].cpu().numpy()
     return Result(I=h[:, 0], var=h[:, 1], Ibar=r["Ibar"], sigbar=r["sigbar"], chi2dof=r["chi2dof"],

@@ -37,11 +37,14 @@ class Grid:
         kw = dict(device=self.device)
         self.edges = torch.zeros((self.dim, self.nbins + 1), dtype=torch.float64, **kw)
         self.table = torch.zeros((self.dim, self.nbins, 2), dtype=torch.float32, **kw)
-        self.bins = torch.zeros((2, self.dim, self.nbins), dtype=torch.float64, **kw)
+        # the bin sums [2][dim][nbins] head a buffer whose tail is library-private
+        self._bins_buf = torch.zeros(sizes[2] // 8, dtype=torch.float64, **kw)
+        nb = 2 * self.dim * self.nbins
+        self.bins = self._bins_buf[:nb].view(2, self.dim, self.nbins)
         self.scal = torch.zeros(L.SCAL_LEN, dtype=torch.float64, **kw)
         assert self.edges.numel() * 8 == sizes[0] and self.table.numel() * 4 == sizes[1]
-        assert self.bins.numel() * 8 == sizes[2] and self.scal.numel() * 8 == sizes[3]
-        L.call("vmc_bind", h, _ptr(self.edges), _ptr(self.table), _ptr(self.bins), _ptr(self.scal))
+        assert self.scal.numel() * 8 == sizes[3]
+        L.call("vmc_bind", h, _ptr(self.edges), _ptr(self.table), _ptr(self._bins_buf), _ptr(self.scal))
         self.ng = 1
         self.reset()
 
@@ -62,6 +65,17 @@ class Grid:
     def stratify(self, ng: int):
         L.call("bases_stratify", self._h, int(ng))
         self.ng = max(int(ng), 1)
+
+    def bind_cube_max(self, buf: torch.Tensor | None):
+        """Record each cube's largest weight of every stratified forward pass
+        into buf (float64, ng^dim entries, caller zeroes it); None unbinds."""
+        if buf is None:
+            L.call("bases_cube_max", self._h, None, 0)
+            self._cube_max = None
+            return
+        assert buf.dtype == torch.float64 and buf.is_contiguous() and buf.device.type == "cuda"
+        L.call("bases_cube_max", self._h, _ptr(buf), buf.numel())
+        self._cube_max = buf  # keep the memory alive while bound
 
     def set_schedule(self, block_samples: int = 0, chunks_per_cube: int = 0):
         L.call("vmc_set_schedule", self._h, int(block_samples), int(chunks_per_cube))

@@ -240,3 +240,37 @@ def test_error_paths_on_device():
     with pytest.raises(VmcError) as e:
         g5.adjoint(W.LINEAR, (), 1000, 1, 0)
     assert e.value.name in ("VMC_E_DIM", "VMC_E_INTEGRAND")
+
+
+def test_accumulator_state_across_calls():
+    """Every pass leaves the library-private tail of the bins buffer (the
+    blocks' partial sums and the work counter) at zero; repeated iterations
+    without refinement, adjoint passes in between and refinement all leave
+    the next pass correct; buffers bound with arbitrary contents in the tail
+    are cleared before their first pass."""
+    from paper_1010_2107_amd import _lib as L
+    from paper_1010_2107_amd.grid import _ptr
+    announce("accumulator state")
+    d, N, theta, ncall = 3, 32, (0.3, 0.7, 0.12), 50_001
+    nb = 2 * d * N
+    g = Grid(d, N)
+    edges = O.uniform_edges(d, N)
+    for rep in range(3):  # the same iteration three times, no refinement between
+        g.iterate(W.DGAUSS, theta, ncall, 9, 2, fp64=True)
+        ref = O.iterate(W.DGAUSS, edges, theta, ncall, 9, 2)
+        assert rel(g.result()["S1"], ref["S1"]) <= 1e-12, rep
+        assert normwise(g.bins.cpu().numpy(), ref["bins"]) <= 1e-12, rep
+        assert not g._bins_buf[nb:].any().item(), rep
+    g.adjoint(W.DGAUSS, theta, ncall, 9, 2, fp64=True)
+    assert not g._bins_buf[nb:].any().item()
+    assert normwise(g.bins.cpu().numpy(), ref["bins"]) <= 1e-12  # adjoint leaves the bin sums
+    g.refine(1.5)
+    e = g.get_edges()
+    # rebind over garbage in the private tail: the first pass clears it
+    g._bins_buf[nb:].fill_(7.0)
+    L.call("vmc_bind", g.handle, _ptr(g.edges), _ptr(g.table), _ptr(g._bins_buf), _ptr(g.scal))
+    g.iterate(W.DGAUSS, theta, ncall, 9, 3, fp64=True)
+    ref = O.iterate(W.DGAUSS, e, theta, ncall, 9, 3)
+    assert rel(g.result()["S1"], ref["S1"]) <= 1e-12
+    assert normwise(g.bins.cpu().numpy(), ref["bins"]) <= 1e-12
+    assert not g._bins_buf[nb:].any().item()

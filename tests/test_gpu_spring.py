@@ -1,0 +1,258 @@
+"""GPU parity of SPRING event generation (paper Sec. 3.1: the BASES
+integration phase feeds event generation) against the FP64 oracle, through
+the C ABI.
+
+  * per-cube maxima of stratified forward passes, FP64 instantiation: 1e-12
+    relative per cube (the weights differ only by rounding);
+  * the set-up from a given array of maxima: envelope quanta, running sums,
+    the header's total and quantum bit-exact (integer work, and one IEEE
+    division and ceil per cube on both sides); the guide table checked
+    entry by entry against the oracle's cube choice;
+  * events, FP64 instantiation: the same kept trials and the same counts;
+    points within 1e-12;
+  * events, FP32 integrand: the keep decision compares an FP32 weight with
+    u g, so trials whose oracle margin |w - u g| is within 2e-5 of the
+    weight may flip; every other trial must agree, points within 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1010_2107_amd import VmcError
+from paper_1010_2107_amd import _lib as L
+from paper_1010_2107_amd import workloads as W
+from paper_1010_2107_amd.grid import Grid
+from paper_1010_2107_amd.spring import Spring
+from tests.gpu_util import announce, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+TWO64 = 1 << 64
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _grid_edges(rng, d, N):
+    w = rng.gamma(1.0, size=(d, N)) + 0.05
+    e = np.concatenate([np.zeros((d, 1)), np.cumsum(w, axis=1)], axis=1)
+    e /= e[:, -1:]
+    e[:, -1] = 1.0
+    return e
+
+
+@pytest.mark.parametrize("case", [("dgauss_d3_ng4", W.DGAUSS, 3, 32, 4, (0.3, 0.7, 0.12)),
+                                  ("axes_d2_ng3_n50", W.GAUSS_AXES, 2, 50, 3, (0.4, 0.6, 0.1))],
+                         ids=lambda c: c[0])
+def test_cube_max_matches_oracle(case):
+    name, iid, d, N, ng, th = case
+    announce(f"cube max {name}")
+    e = _grid_edges(np.random.default_rng(4), d, N)
+    M = ng ** d
+    ncall = M * 37 + 5
+    g = Grid(d, N)
+    g.stratify(ng)
+    g.set_edges(e)
+    buf = torch.zeros(M, dtype=torch.float64, device="cuda")
+    g.bind_cube_max(buf)
+    ref = np.zeros(M)
+    for it in range(2):
+        g.iterate(iid, th, ncall, 17, it, fp64=True)
+        O.cube_max(iid, e, th, ncall, 17, it, ng, ref)
+        r = O.iterate(iid, e, th, ncall, 17, it, ng=ng)
+        assert abs(g.result()["S1"] / r["S1"] - 1) <= 1e-12
+        g.refine(0.0)  # alpha = 0 keeps the grid
+    got = buf.cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 1e-12 * np.abs(ref))
+    # unbound: the buffer is left alone
+    g.bind_cube_max(None)
+    g.iterate(iid, th, ncall, 17, 5, fp64=True)
+    assert np.array_equal(buf.cpu().numpy(), got)
+    # too small a buffer is refused at iterate time
+    g.bind_cube_max(torch.zeros(M - 1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(VmcError) as ei:
+        g.iterate(iid, th, ncall, 17, 6, fp64=True)
+    assert ei.value.name == "VMC_E_INVALID"
+
+
+def _random_maxima(rng, M):
+    w = rng.lognormal(0.0, 2.0, size=M)
+    w[rng.random(M) < 0.1] = 0.0
+    w[rng.random(M) < 0.01] = -1.0
+    w[rng.random(M) < 0.01] = np.nan
+    return w
+
+
+@pytest.mark.parametrize("shape", [(3, 3, 8), (2, 2, 8), (8, 4, 16), (10, 4, 8), (1, 2, 4)],
+                         ids=["M27", "M4", "M65536", "M1048576", "M2"])
+def test_setup_matches_oracle(shape):
+    d, ng, N = shape
+    M = ng ** d
+    announce(f"spring setup M={M}")
+    g = Grid(d, N)
+    g.stratify(ng)
+    sp = Spring(g)
+    assert sp.ncubes == M
+    w = _random_maxima(np.random.default_rng(M), M)
+    sp.setup(torch.from_numpy(w).cuda())
+    q_ref, unit_ref = O.spring_envelope(w)
+    h = sp.header()
+    assert h["unit"] == unit_ref and h["gmax"] == np.nanmax(w) and h["total"] == int(q_ref.sum())
+    assert h["ncubes"] == M and (1 << h["kbits"]) >= M and (h["kbits"] == 0 or (1 << (h["kbits"] - 1)) < M)
+    assert h["trials"] == h["kept"] == h["over"] == h["slot"] == 0
+    assert h["env"] == float(q_ref.sum()) * unit_ref / M
+    assert np.array_equal(sp.quanta(), q_ref)
+    P = sp.prefix.cpu().numpy().view(np.uint64)
+    assert P[0] == 0 and np.array_equal(P[1:], np.cumsum(q_ref, dtype=np.uint64))
+    guide = sp.guide.cpu().numpy().view(np.uint32)
+    K = 1 << h["kbits"]
+    assert guide.size >= K + 1
+    bs = np.unique(np.concatenate([np.arange(min(K, 64)), np.linspace(0, K - 1, 200).astype(np.int64)]))
+    for b in bs:
+        r64 = (int(b) << (64 - h["kbits"])) if h["kbits"] else 0
+        assert guide[b] == O.spring_pick(q_ref, r64), b
+    assert guide[K] == O.spring_pick(q_ref, TWO64 - 1)
+
+
+@pytest.fixture(scope="module")
+def gauss2():
+    """A BASES grid and cube maxima from the oracle for the 2-D per-axis
+    Gaussian product (ng = 8, 64 cubes)."""
+    th = (0.35, 0.6, 0.15)
+    ng = 8
+    run = O.integrate(W.GAUSS_AXES, 2, 32, th, 8 * 8 * 1000, 4, 21, ng=ng, itmx2=2, cube_max_phase2=True)
+    q, unit = O.spring_envelope(run.wmax)
+    return dict(th=th, ng=ng, edges=run.edges, wmax=run.wmax, q=q, unit=unit)
+
+
+def _gpu_spring(G):
+    g = Grid(2, 32)
+    g.stratify(G["ng"])
+    g.set_edges(G["edges"])
+    sp = Spring(g)
+    sp.setup(torch.from_numpy(G["wmax"]).cuda())
+    return g, sp
+
+
+def _run(sp, th, seed, pass_, ranges, cap, fp64):
+    dt = torch.float64 if fp64 else torch.float32
+    ev = torch.zeros((cap, 2), dtype=dt, device="cuda")
+    tr = torch.full((cap,), -1, dtype=torch.int64, device="cuda")
+    for t0, n in ranges:
+        sp.generate(W.GAUSS_AXES, th, seed, pass_, t0, n, ev, tr, fp64=fp64)
+    h = sp.header()
+    n = min(h["slot"], cap)
+    trials = tr[:n].cpu().numpy()
+    order = np.argsort(trials)
+    return h, trials[order], ev[:n].cpu().numpy().astype(np.float64)[order]
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_events_match_oracle(gauss2, fp64):
+    announce(f"spring events fp64={fp64}")
+    G = gauss2
+    g, sp = _gpu_spring(G)
+    ranges = [(0, 100_000), (100_000, 60_000), ((1 << 32) - 3000, 6000)]  # the last crosses 2^32
+    h, trials, x = _run(sp, G["th"], 7, 3, ranges, 200_000, fp64)
+    ref = [O.spring_trials(W.GAUSS_AXES, G["edges"], G["th"], G["ng"], G["q"], G["unit"], 7, 3, t0, n)
+           for t0, n in ranges]
+    all_t = np.concatenate([np.arange(t0, t0 + n, dtype=np.int64) for t0, n in ranges])
+    kept = np.concatenate([r["kept"] for r in ref])
+    xr = np.concatenate([r["x"] for r in ref])
+    w = np.concatenate([r["w"] for r in ref])
+    ug = np.concatenate([r["u"] * r["env"] for r in ref])
+    over = np.concatenate([r["w"] > r["env"] for r in ref])
+    assert h["trials"] == all_t.size
+    assert h["slot"] == h["kept"] == len(trials)
+    if fp64:
+        assert np.array_equal(trials, all_t[kept])
+        assert h["kept"] == kept.sum() and h["over"] == over.sum()
+        assert np.max(np.abs(x - xr[kept])) <= 1e-12
+    else:
+        margin = np.abs(w - ug) <= 2e-5 * np.maximum(np.abs(w), ug)
+        got = np.isin(all_t, trials)
+        assert np.all(got[~margin] == kept[~margin])
+        assert np.sum(got != kept) <= max(3, margin.sum())
+        common = np.isin(trials, all_t[kept])
+        idx = np.searchsorted(all_t, trials[common])
+        assert np.max(np.abs(x[common] - xr[idx])) <= 1e-5
+    # the trial numbers are unique and every stored point lies in [0, 1]
+    assert np.unique(trials).size == trials.size
+    assert np.all((x >= 0) & (x <= 1))
+
+
+def test_capacity_counts_and_clear(gauss2):
+    announce("spring capacity")
+    G = gauss2
+    g, sp = _gpu_spring(G)
+    h, trials, x = _run(sp, G["th"], 5, 0, [(0, 50_000)], 1000, True)
+    ref = O.spring_trials(W.GAUSS_AXES, G["edges"], G["th"], G["ng"], G["q"], G["unit"], 5, 0, 0, 50_000)
+    assert h["kept"] == ref["kept"].sum() == h["slot"] > 1000
+    assert trials.size == 1000 and np.all(ref["kept"][trials])
+    assert np.max(np.abs(x - ref["x"][trials])) <= 1e-12
+    sp.clear_counts()
+    h = sp.header()
+    assert h["trials"] == h["kept"] == h["over"] == h["slot"] == 0 and h["total"] == int(G["q"].sum())
+
+
+def test_error_paths(gauss2):
+    announce("spring errors")
+    G = gauss2
+    g = Grid(2, 32)
+    with pytest.raises(VmcError) as ei:
+        Spring(g)  # plain grid
+    assert ei.value.name == "VMC_E_STRAT"
+    g.stratify(G["ng"])
+    sp = Spring(g)
+    ev = torch.zeros((10, 2), dtype=torch.float32, device="cuda")
+    with pytest.raises(VmcError) as ei:
+        sp.generate(W.GAUSS_AXES, G["th"], 1, 0, 0, 100, ev)  # no set-up yet
+    assert ei.value.name == "VMC_E_SPRING"
+    for bad in (np.zeros(64), np.full(64, np.nan), np.r_[np.ones(63), np.inf]):
+        with pytest.raises(VmcError) as ei:
+            sp.setup(torch.from_numpy(bad).cuda())
+        assert ei.value.name == "VMC_E_SPRING"
+    sp.setup(torch.from_numpy(G["wmax"]).cuda())
+    sp.generate(W.GAUSS_AXES, G["th"], 1, 0, 0, 100, ev)
+    with pytest.raises(VmcError) as ei:
+        sp.generate(W.GAUSS_AXES, (0.5,), 1, 0, 0, 100, ev)
+    assert ei.value.name == "VMC_E_PARAMS"
+    g.stratify(4)  # another stratification invalidates the set-up
+    with pytest.raises(VmcError) as ei:
+        sp.generate(W.GAUSS_AXES, G["th"], 1, 0, 0, 100, ev)
+    assert ei.value.name == "VMC_E_SPRING"
+
+
+def test_bases_then_spring_physics():
+    """W + 2 partons: BASES with the cube maxima of its integration phase,
+    then SPRING on the GPU.  Every kept event passes the cuts (w > 0), and
+    the keep rate is at most the integral over the envelope integral."""
+    announce("bases + spring wjets2")
+    from paper_1010_2107_amd.driver import integrate
+    d, N, ng = 10, 64, 2
+    buf = torch.zeros(ng ** d, dtype=torch.float64, device="cuda")
+    res = integrate(W.WJETS, d, N, W.WJETS_THETA, 2_000_000, 5, 1234, ng=ng, itmx2=3, cube_max=buf)
+    g = res.grid
+    sp = Spring(g)
+    sp.setup(buf)
+    n = 4_000_000
+    ev = torch.zeros((n // 4, d), dtype=torch.float32, device="cuda")
+    tr = torch.zeros(n // 4, dtype=torch.int64, device="cuda")
+    sp.generate(W.WJETS, W.WJETS_THETA, 99, 0, 0, n, ev, tr)
+    h = sp.header()
+    assert h["trials"] == n and 0 < h["kept"] <= n // 4
+    rate = h["kept"] / n
+    expect = res.Ibar / h["env"]
+    sig = np.sqrt(rate * (1 - rate) / n) + expect * res.sigbar / res.Ibar
+    # the maxima of a peaked integrand seen in 3 x 2e6 samples are
+    # underestimates for some cubes: those trials overflow and the keep rate
+    # falls below I / envelope by the overflowed weight
+    assert h["over"] < 0.15 * h["kept"]
+    assert rate < expect + 5 * sig and rate > 0.7 * expect
+    # a sample of kept events re-evaluated by the oracle: all inside the cuts
+    x = ev[:200].cpu().numpy().astype(np.float64)
+    for xi in x:
+        assert O.integrand(W.WJETS, xi, W.WJETS_THETA) > 0.0
