@@ -19,6 +19,8 @@
  */
 #include "vmc_oracle.h"
 
+#include <complex.h>
+#undef I /* the imaginary unit is written _Complex_I; I is a result field */
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -195,6 +197,7 @@ int orc_integrand_nparams(int id, int d)
     case ORC_GAUSS_AXES: return d + 1;
     case ORC_WJETS: return 7;
     case ORC_PSVOL: return 2;
+    case ORC_WHEL: return 8;
     default: return ORC_E_INTEGRAND;
     }
 }
@@ -209,6 +212,7 @@ int orc_integrand_ngrad(int id, int d)
     case ORC_GAUSS_AXES: return d + 1;
     case ORC_WJETS: return 3;
     case ORC_PSVOL: return 0;
+    case ORC_WHEL: return 3;
     default: return ORC_E_INTEGRAND;
     }
 }
@@ -461,6 +465,291 @@ double orc_wjets_event(int d, const double *x, const double *theta, int ntheta,
     return f;
 }
 
+/* ===================================================================== */
+/* The paper's process, u dbar -> W+(-> mu+ nu) + n gluons (Sec. 5, eq. 1; */
+/* Table 4: 1, 2 and 8 diagrams for n = 0, 1, 2), from tree-level          */
+/* helicity amplitudes.  All fermions are massless and the W couples only */
+/* to left-handed fermions, so the quark line and the lepton line are     */
+/* chains of 2x2 blocks acting on left-chirality Weyl spinors:            */
+/*   vertex with vector V:  V_mu sigmabar^mu;  propagator P: P_mu sigma^mu */
+/*   / P^2;  line = v_L(p_dbar)^dagger [...] u_L(p_u).                    */
+/* Feynman rules (Feynman gauge): quark-gluon  i g_s gamma^mu T^a; three- */
+/* gluon  g_s f^abc [g^{mu nu}(k-p)^rho + g^{nu rho}(p-q)^mu +            */
+/* g^{rho mu}(q-k)^nu] (momenta incoming); quark propagator i pslash/p^2; */
+/* gluon propagator -i g/k^2; W: i g_W/sqrt2 gamma^mu P_L at each line,   */
+/* propagator -i g/(q^2 - M^2 + i M Gamma) (the q q term vanishes on the   */
+/* massless lepton current).  Colour: M = sum over orderings sigma of      */
+/* (T^{a_sigma1} .. T^{a_sigman})_{ji} A_sigma with f^abc T^c =            */
+/* -i [T^a, T^b]; the colour sum of |M|^2 is A^dagger C A with C = 3       */
+/* (n=0), 4 (n=1), [[16/3, -2/3], [-2/3, 16/3]] (n=2).                     */
+/* ===================================================================== */
+typedef double complex cplx;
+
+#define WHEL_GF 1.1663787e-5 /* Fermi constant, GeV^-2                    */
+#define WHEL_MWREF 80.4      /* g_W^2 = 4 sqrt2 G_F MWREF^2 (fixed coupling) */
+
+static double whel_gw2(void) { return 4.0 * sqrt(2.0) * WHEL_GF * WHEL_MWREF * WHEL_MWREF; }
+
+/* left-chirality spinor of a massless momentum: p.sigmabar u = 0, u^dagger u = 2 E */
+static void weyl_spinor(const double p[4], cplx u[2])
+{
+    double pp = p[0] + p[3], pm = p[0] - p[3];
+    if (pp >= pm) {
+        double r = sqrt(pp);
+        u[0] = -(p[1] - _Complex_I * p[2]) / r;
+        u[1] = r;
+    } else {
+        double r = sqrt(pm);
+        u[0] = r;
+        u[1] = -(p[1] + _Complex_I * p[2]) / r;
+    }
+}
+
+/* x <- (a_mu sigmabar^mu) x, a contravariant */
+static void apply_sbar(const cplx a[4], cplx x[2])
+{
+    cplx y0 = (a[0] + a[3]) * x[0] + (a[1] - _Complex_I * a[2]) * x[1];
+    cplx y1 = (a[1] + _Complex_I * a[2]) * x[0] + (a[0] - a[3]) * x[1];
+    x[0] = y0;
+    x[1] = y1;
+}
+
+/* x <- (a_mu sigma^mu) x */
+static void apply_sig(const cplx a[4], cplx x[2])
+{
+    cplx y0 = (a[0] - a[3]) * x[0] - (a[1] - _Complex_I * a[2]) * x[1];
+    cplx y1 = -(a[1] + _Complex_I * a[2]) * x[0] + (a[0] + a[3]) * x[1];
+    x[0] = y0;
+    x[1] = y1;
+}
+
+static double rdot(const double a[4], const double b[4]) { return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3]; }
+static cplx cdot(const cplx a[4], const cplx b[4]) { return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3]; }
+static cplx cdot_r(const double a[4], const cplx b[4]) { return a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3]; }
+
+/* One quark line: vertices V[0..k-1] from the u end, V[i] carrying away
+ * momentum out[i]; propagators between them. */
+static cplx quark_line(int k, const cplx *const *V, const double *const *out, const cplx uL[2],
+                       const cplx vL[2], const double pu[4])
+{
+    cplx x[2] = {uL[0], uL[1]};
+    double P[4] = {pu[0], pu[1], pu[2], pu[3]};
+    for (int i = 0; i < k; ++i) {
+        if (i > 0) {
+            cplx Pc[4] = {P[0], P[1], P[2], P[3]};
+            apply_sig(Pc, x);
+            double P2 = rdot(P, P);
+            x[0] /= P2;
+            x[1] /= P2;
+        }
+        apply_sbar(V[i], x);
+        for (int c = 0; c < 4; ++c) P[c] -= out[i][c];
+    }
+    return conj(vL[0]) * x[0] + conj(vL[1]) * x[1];
+}
+
+int orc_whel_partials(int n, const double *mom, const double *eps, double *A)
+{
+    /* mom: pu, pd, k_1..k_n, p_mu, p_nu (4 each); eps: per gluon the
+     * polarisation vector used at the vertex (re[4], im[4]); A: the
+     * colour-ordered amplitudes (re, im) without couplings and W
+     * propagator: n <= 1 one of them, n = 2 A_12 (colour T^a1 T^a2) and
+     * A_21. */
+    if (n < 0 || n > 2) return ORC_E_INVALID;
+    const double *pu = mom, *pd = mom + 4, *pmu = mom + 4 * (n + 2), *pnu = mom + 4 * (n + 3);
+    cplx uL[2], vL[2], a[2], b[2];
+    weyl_spinor(pu, uL);
+    weyl_spinor(pd, vL);
+    weyl_spinor(pnu, a);
+    weyl_spinor(pmu, b);
+    /* lepton current L^mu = u_L(nu)^dagger sigmabar^mu v_L(mu), sigmabar = (1, -sigma) */
+    cplx L[4];
+    L[0] = conj(a[0]) * b[0] + conj(a[1]) * b[1];
+    L[1] = -(conj(a[0]) * b[1] + conj(a[1]) * b[0]);
+    L[2] = -(conj(a[0]) * (-_Complex_I * b[1]) + conj(a[1]) * (_Complex_I * b[0]));
+    L[3] = -(conj(a[0]) * b[0] - conj(a[1]) * b[1]);
+    double q[4];
+    for (int c = 0; c < 4; ++c) q[c] = pmu[c] + pnu[c];
+    cplx e[2][4];
+    for (int i = 0; i < n; ++i)
+        for (int c = 0; c < 4; ++c) e[i][c] = eps[8 * i + c] + _Complex_I * eps[8 * i + 4 + c];
+    const double *k1 = mom + 8, *k2 = mom + 12;
+    if (n == 0) {
+        const cplx *V[1] = {L};
+        const double *o[1] = {q};
+        cplx r = quark_line(1, V, o, uL, vL, pu);
+        A[0] = creal(r);
+        A[1] = cimag(r);
+    } else if (n == 1) {
+        const cplx *V1[2] = {e[0], L}, *V2[2] = {L, e[0]};
+        const double *o1[2] = {k1, q}, *o2[2] = {q, k1};
+        cplx r = quark_line(2, V1, o1, uL, vL, pu) + quark_line(2, V2, o2, uL, vL, pu);
+        A[0] = creal(r);
+        A[1] = cimag(r);
+    } else {
+        /* the off-shell gluon of the three-gluon vertex: V^rho / K^2 with
+         * V = (e1.e2)(k2-k1) - 2 (k2.e1) e2 + 2 (k1.e2) e1 */
+        double K[4];
+        for (int c = 0; c < 4; ++c) K[c] = k1[c] + k2[c];
+        cplx e12 = cdot(e[0], e[1]), k2e1 = cdot_r(k2, e[0]), k1e2 = cdot_r(k1, e[1]);
+        double K2 = rdot(K, K);
+        cplx J[4];
+        for (int c = 0; c < 4; ++c) J[c] = (e12 * (k2[c] - k1[c]) - 2.0 * k2e1 * e[1][c] + 2.0 * k1e2 * e[0][c]) / K2;
+        /* colour T^a1 T^a2: gluon 1 nearer the dbar end, i.e. gluon 2 first from the u end */
+        const cplx *Va[3] = {e[1], e[0], L}, *Vb[3] = {e[1], L, e[0]}, *Vc[3] = {L, e[1], e[0]};
+        const double *oa[3] = {k2, k1, q}, *ob[3] = {k2, q, k1}, *oc[3] = {q, k2, k1};
+        cplx A12 = quark_line(3, Va, oa, uL, vL, pu) + quark_line(3, Vb, ob, uL, vL, pu) +
+                   quark_line(3, Vc, oc, uL, vL, pu);
+        const cplx *Wa[3] = {e[0], e[1], L}, *Wb[3] = {e[0], L, e[1]}, *Wc[3] = {L, e[0], e[1]};
+        const double *pa_[3] = {k1, k2, q}, *pb_[3] = {k1, q, k2}, *pc_[3] = {q, k1, k2};
+        cplx A21 = quark_line(3, Wa, pa_, uL, vL, pu) + quark_line(3, Wb, pb_, uL, vL, pu) +
+                   quark_line(3, Wc, pc_, uL, vL, pu);
+        const cplx *T1[2] = {J, L}, *T2[2] = {L, J};
+        const double *t1[2] = {K, q}, *t2[2] = {q, K};
+        cplx T = quark_line(2, T1, t1, uL, vL, pu) + quark_line(2, T2, t2, uL, vL, pu);
+        A12 += T;
+        A21 -= T;
+        A[0] = creal(A12);
+        A[1] = cimag(A12);
+        A[2] = creal(A21);
+        A[3] = cimag(A21);
+    }
+    return ORC_OK;
+}
+
+/* Polarisation vector of gluon momentum k, helicity lam = +-1:
+ * (0, (-lam e1 - i e2)/sqrt2) with e1, e2 the polar and azimuthal unit
+ * vectors of k; returned conjugated (outgoing gluon) as re[4], im[4]. */
+static void gluon_eps_out(const double k[4], int lam, double *re, double *im)
+{
+    double pt = sqrt(k[1] * k[1] + k[2] * k[2]);
+    double kk = sqrt(pt * pt + k[3] * k[3]);
+    double e1[3], e2[3];
+    if (pt > 0.0) {
+        e1[0] = k[3] * k[1] / (kk * pt);
+        e1[1] = k[3] * k[2] / (kk * pt);
+        e1[2] = -pt / kk;
+        e2[0] = -k[2] / pt;
+        e2[1] = k[1] / pt;
+        e2[2] = 0.0;
+    } else {
+        e1[0] = k[3] >= 0.0 ? 1.0 : -1.0;
+        e1[1] = 0.0;
+        e1[2] = 0.0;
+        e2[0] = 0.0;
+        e2[1] = 1.0;
+        e2[2] = 0.0;
+    }
+    double r = 1.0 / sqrt(2.0);
+    re[0] = im[0] = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        re[1 + c] = -lam * e1[c] * r;
+        im[1 + c] = +e2[c] * r; /* conjugate of -i e2 / sqrt2 */
+    }
+}
+
+double orc_whel_me2(int n, const double *mom, int hel, const double *theta)
+{
+    /* colour-summed |M|^2 of gluon helicities hel (bit i set: gluon i has
+     * helicity +1), quark and lepton helicities fixed by the W coupling */
+    double eps[16] = {0};
+    for (int i = 0; i < n; ++i)
+        gluon_eps_out(mom + 4 * (2 + i), ((hel >> i) & 1) ? 1 : -1, eps + 8 * i, eps + 8 * i + 4);
+    double A[4];
+    if (orc_whel_partials(n, mom, eps, A)) return NAN;
+    double cs;
+    if (n == 0)
+        cs = 3.0 * (A[0] * A[0] + A[1] * A[1]);
+    else if (n == 1)
+        cs = 4.0 * (A[0] * A[0] + A[1] * A[1]);
+    else {
+        double a2 = A[0] * A[0] + A[1] * A[1], b2 = A[2] * A[2] + A[3] * A[3];
+        double re_ab = A[0] * A[2] + A[1] * A[3];
+        cs = (16.0 / 3.0) * (a2 + b2) - (4.0 / 3.0) * re_ab;
+    }
+    double M = theta[0], Gam = theta[1], gs = theta[2];
+    const double *pmu = mom + 4 * (n + 2), *pnu = mom + 4 * (n + 3);
+    double q[4];
+    for (int c = 0; c < 4; ++c) q[c] = pmu[c] + pnu[c];
+    double q2 = rdot(q, q);
+    double D = (q2 - M * M) * (q2 - M * M) + M * M * Gam * Gam;
+    double gw2 = whel_gw2();
+    return pow(gs, 2.0 * n) * (gw2 * gw2 / 4.0) * cs / D;
+}
+
+int orc_whel_pass_cuts(int n, const double *p, double y_boost, double ptmin, double eta_mu, double eta_g,
+                       double ptij_min)
+{
+    /* p: final state in the partonic frame, order g_1..g_n, mu+, nu */
+    for (int i = 0; i <= n; ++i) {
+        const double *v = p + 4 * i;
+        double pt = pt_of(v);
+        double eta = eta_of(v) + y_boost;
+        if (!(pt > ptmin)) return 0;
+        if (!(fabs(eta) < (i < n ? eta_g : eta_mu))) return 0;
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const double *a = p + 4 * i, *b = p + 4 * j;
+            double deta = eta_of(a) - eta_of(b);
+            double dphi = fabs(phi_of(a) - phi_of(b));
+            if (dphi > M_PI) dphi = 2.0 * M_PI - dphi;
+            double dr = sqrt(deta * deta + dphi * dphi);
+            double ptij = fmin(pt_of(a), pt_of(b)) * dr;
+            if (!(ptij > ptij_min)) return 0;
+        }
+    return 1;
+}
+
+double orc_whel_event(int d, const double *x, const double *theta, int ntheta, double *p, double *aux,
+                      double *grad)
+{
+    int n = (d - 5) / 3; /* gluons */
+    int nf = n + 2;      /* final state: g_1..g_n, mu+, nu */
+    (void)ntheta;
+    double M = theta[0], Gam = theta[1], gs = theta[2], sqrtS = theta[3], ptmin = theta[4];
+    double eta_mu = theta[5], eta_g = theta[6], ptij_min = theta[7];
+    double S = sqrtS * sqrtS;
+    double tau0 = ((1.0 + n) * ptmin) * ((1.0 + n) * ptmin) / S;
+    double L = log(tau0);
+    double x1 = exp(L * (1.0 - x[0]));
+    double x2 = exp(L * x[0] * (1.0 - x[1]));
+    double Jx = L * L * x[0] * x1 * x2;
+    double shat = x1 * x2 * S;
+    double lum = toy_pdf(x1) * toy_pdf(x2);
+    double Vn = orc_rambo_diet(nf, sqrt(shat), x + 2, p);
+    double y_boost = 0.5 * log(x1 / x2);
+    /* helicity sampling: the last variable picks one of the 2^n gluon
+     * helicity configurations, weight 2^n */
+    int nh = 1 << n;
+    int hel = (int)(x[d - 1] * nh);
+    if (hel >= nh) hel = nh - 1;
+    if (grad) grad[0] = grad[1] = grad[2] = 0.0;
+    if (aux) {
+        aux[0] = x1; aux[1] = x2; aux[2] = shat; aux[3] = Jx;
+        aux[4] = lum; aux[5] = Vn; aux[6] = 2.0 * mdot(p + 4 * n, p + 4 * (n + 1)); aux[7] = 0.0;
+    }
+    if (!orc_whel_pass_cuts(n, p, y_boost, ptmin, eta_mu, eta_g, ptij_min)) return 0.0;
+    if (aux) aux[7] = 1.0;
+    double rs = sqrt(shat);
+    double mom[4 * 6];
+    double pu[4] = {0.5 * rs, 0.0, 0.0, 0.5 * rs}, pd[4] = {0.5 * rs, 0.0, 0.0, -0.5 * rs};
+    memcpy(mom, pu, sizeof pu);
+    memcpy(mom + 4, pd, sizeof pd);
+    memcpy(mom + 8, p, 4 * (size_t)nf * sizeof(double));
+    double me2 = orc_whel_me2(n, mom, hel, theta);
+    /* spin (1/4) and colour (1/9) average of the initial state */
+    double f = lum * Jx * Vn / (2.0 * shat) * (nh / 36.0) * me2;
+    if (grad) {
+        double q2 = aux ? aux[6] : 2.0 * mdot(p + 4 * n, p + 4 * (n + 1));
+        double D = (q2 - M * M) * (q2 - M * M) + M * M * Gam * Gam;
+        grad[0] = f * (4.0 * M * (q2 - M * M) - 2.0 * M * Gam * Gam) / D;
+        grad[1] = f * (-2.0 * M * M * Gam / D);
+        grad[2] = f * (2.0 * n / gs);
+    }
+    return f;
+}
+
 double orc_integrand(int id, int d, const double *x, const double *theta, int ntheta, double *grad)
 {
     switch (id) {
@@ -507,6 +796,10 @@ double orc_integrand(int id, int d, const double *x, const double *theta, int nt
         double p[4 * ORC_MAXM];
         return orc_wjets_event(d, x, theta, ntheta, p, NULL, grad);
     }
+    case ORC_WHEL: {
+        double p[4 * ORC_MAXM];
+        return orc_whel_event(d, x, theta, ntheta, p, NULL, grad);
+    }
     default:
         return NAN;
     }
@@ -520,6 +813,7 @@ static int check_integrand(int id, int d, int ntheta)
     if (id == ORC_WJETS || id == ORC_PSVOL) {
         if (d < 7 || (d - 4) % 3 != 0 || (d - 4) / 3 > ORC_MAXM - 2) return ORC_E_DIM;
     }
+    if (id == ORC_WHEL && d != 5 && d != 8 && d != 11) return ORC_E_DIM;
     return ORC_OK;
 }
 

@@ -43,7 +43,8 @@ enum {
     ORC_DGAUSS = 3,     /* double Gaussian, theta=(c1,c2,s)              */
     ORC_GAUSS_AXES = 4, /* prod_a phi(x_a;c_a,s)/(s sqrt(pi)), theta=(c_0..c_{d-1},s) */
     ORC_WJETS = 5,      /* W(->e nu) + n_p partons toy cross section     */
-    ORC_PSVOL = 6       /* PDF x phase-space weight only (no cuts, |M|^2=1) */
+    ORC_PSVOL = 6,      /* PDF x phase-space weight only (no cuts, |M|^2=1) */
+    ORC_WHEL = 7        /* u dbar -> W+(-> mu+ nu) + n gluons, helicity amplitudes, d = 3n+5 */
 };
 
 /* Error codes returned by the int-valued functions. */
@@ -96,6 +97,20 @@ int orc_num_cycles(int m);
  * and aux = {x1, x2, shat, Jx, lum, Vn, m_enu^2, pass}; returns f (0 when cut). */
 double orc_wjets_event(int d, const double *x, const double *theta, int ntheta,
                        double *p, double *aux, double *grad);
+
+/* u dbar -> W+(-> mu+ nu) + n gluons (n = (d-5)/3 <= 2), see the .c file.
+ * theta = (M_W, Gamma_W, g_s, sqrtS, pTmin, etamax_mu, etamax_g, pTij_min).
+ *  orc_whel_partials: colour-ordered amplitudes for given momenta (pu, pd,
+ *    k_1..k_n, p_mu, p_nu) and gluon polarisation vectors (re[4], im[4] each)
+ *  orc_whel_me2: colour-summed |M|^2 for gluon helicity bits hel
+ *  orc_whel_event: f at x[d], momenta p[(n+2)][4] (g.., mu, nu; partonic
+ *    frame), aux as orc_wjets_event; grad w.r.t. (M_W, Gamma_W, g_s) */
+int orc_whel_partials(int n, const double *mom, const double *eps, double *A);
+double orc_whel_me2(int n, const double *mom, int hel, const double *theta);
+int orc_whel_pass_cuts(int n, const double *p, double y_boost, double ptmin, double eta_mu, double eta_g,
+                       double ptij_min);
+double orc_whel_event(int d, const double *x, const double *theta, int ntheta, double *p, double *aux,
+                      double *grad);
 
 /* ------------------------------------------------------------ iteration */
 typedef struct {
