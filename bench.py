@@ -206,6 +206,119 @@ def batched_leg():
             "max_z_vs_closed_form": float(max(zs)), "all_within_3_sigma": bool(max(zs) < 3)}
 
 
+def spring_leg(trials=50_000_000):
+    """SPRING event generation after a BASES run whose integration phase
+    records the cube maxima: trials/s and kept events/s of one
+    spring_generate launch, for the double Gaussian (d=8, 4^8 cubes) and for
+    W + 2 partons (d=10, 2^10 cubes)."""
+    import torch
+
+    from paper_1010_2107_amd import workloads as W
+    from paper_1010_2107_amd.driver import integrate
+    from paper_1010_2107_amd.spring import Spring
+
+    out = {}
+    cases = [(W.C2, W.C2.ncall, W.C2.ng, W.C2.itmx, W.C2.itmx2),
+             (W.C3, 2_000_000, 2, 5, 3)]
+    for w, ncall, ng, itmx, itmx2 in cases:
+        name = w.name if w is W.C2 else f"{w.name.split('_vegas')[0]}_bases_ng{ng}"
+        buf = torch.zeros(ng ** w.dim, dtype=torch.float64, device="cuda")
+        res = integrate(w.integrand, w.dim, w.nbins, w.theta, ncall, itmx, w.seed, ng=ng, itmx2=itmx2, cube_max=buf)
+        sp = Spring(res.grid)
+        t0 = time.perf_counter()
+        sp.setup(buf)
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        cap = 1 << 22
+        ev = torch.empty((cap, w.dim), dtype=torch.float32, device="cuda")
+        tr = torch.empty(cap, dtype=torch.int64, device="cuda")
+        sp.generate(w.integrand, w.theta, 7, 0, 0, 1 << 20, ev, tr)  # warm-up
+        sp.clear_counts()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sp.generate(w.integrand, w.theta, 7, 1, 0, trials, ev, tr)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        h = sp.header()
+        out[name] = {"trials": h["trials"], "kept": h["kept"], "overflow": h["over"],
+                     "stored": min(h["slot"], cap), "ms": ms, "trials_per_s": h["trials"] / (ms / 1e3),
+                     "events_per_s": h["kept"] / (ms / 1e3), "efficiency": h["kept"] / h["trials"],
+                     "expected_efficiency": res.Ibar / h["env"], "cubes": h["ncubes"], "setup_ms": setup_ms,
+                     "bases": {"ncall": ncall, "itmx1": itmx, "itmx2": itmx2, "Ibar": res.Ibar,
+                               "sigbar": res.sigbar}}
+        print(f"[bench] spring {name}: {out[name]['events_per_s']:.4g} events/s "
+              f"({out[name]['trials_per_s']:.4g} trials/s)", file=sys.stderr, flush=True)
+    return out
+
+
+def host_accumulation_leg(iters=3):
+    """The paper's split of the work (Sec. 3.2): the GPU generates the
+    points and evaluates the integrand, the weights and bin indices are
+    copied to the host, and the host accumulates the sums and per-bin sums.
+    Here the host side is numpy (FP64), the refinement stays on the GPU
+    (its cost is negligible either way).  Same workload and grid as the
+    GPU-resident path, which is timed beside it."""
+    import numpy as np
+    import torch
+
+    from paper_1010_2107_amd import workloads as W
+    from paper_1010_2107_amd.grid import Grid
+
+    w = W.C2_PLAIN
+    d, N, n = w.dim, w.nbins, w.ncall
+    g = Grid(d, N)
+    th = g.theta_tensor(w.theta)
+    words = torch.empty((n, d), dtype=torch.int32, device="cuda")
+    wt = torch.empty(n, dtype=torch.float32, device="cuda")
+    w_h = torch.empty(n, dtype=torch.float32, pin_memory=True)
+    j_h = torch.empty((n, d), dtype=torch.uint8, pin_memory=True)
+    split = {"gpu_ms": 0.0, "d2h_ms": 0.0, "host_ms": 0.0, "refine_ms": 0.0}
+    rel = 0.0
+    for it in range(iters + 1):
+        timed = it > 0  # the first iteration is warm-up
+        t0 = time.perf_counter()
+        g.dump_into(w.integrand, th, n, w.seed, it, 0, words=words, w=wt)
+        # bin index of each word (the words are unsigned 32-bit, held in int32)
+        m = torch.bitwise_right_shift(words.to(torch.int64) & 0xFFFFFFFF, 9) * 2 + 1
+        j = torch.bitwise_right_shift(m * N, 24).to(torch.uint8)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        w_h.copy_(wt, non_blocking=True)
+        j_h.copy_(j, non_blocking=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        wv = w_h.numpy().astype(np.float64)
+        jv = j_h.numpy()
+        S1, S2 = wv.sum(), (wv * wv).sum()
+        bins = np.zeros((2, d, N))
+        for a in range(d):
+            bins[0, a] = np.bincount(jv[:, a], weights=wv, minlength=N)
+            bins[1, a] = np.bincount(jv[:, a], weights=wv * wv, minlength=N)
+        I = S1 / n
+        var = (S2 / n - I * I) / (n - 1)
+        t3 = time.perf_counter()
+        if it == 1:  # the GPU-resident pass on the same grid and samples
+            g.iterate(w.integrand, th, n, w.seed, it)
+            r = g.result()
+            rel = max(abs(r["S1"] - S1) / abs(S1), abs(r["S2"] - S2) / S2)
+        t4 = time.perf_counter()
+        g.bins.copy_(torch.from_numpy(bins))
+        g.refine(w.alpha)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        if timed:
+            split["gpu_ms"] += (t1 - t0) * 1e3
+            split["d2h_ms"] += (t2 - t1) * 1e3
+            split["host_ms"] += (t3 - t2) * 1e3
+            split["refine_ms"] += (t5 - t4) * 1e3
+    total_ms = sum(split.values())
+    return {"workload": w.name, "iterations": iters, "evals_per_s": n * iters / (total_ms / 1e3),
+            "ms_per_iteration": {k: v / iters for k, v in split.items()},
+            "bytes_d2h_per_iteration": n * (4 + d), "host_cores": 1,
+            "max_rel_diff_vs_gpu_sums": rel, "estimate_last_iteration": {"I": I, "var": var}}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +415,15 @@ def main(argv=None):
         line["secondary"] = sec
         print("[bench] batched leg", file=sys.stderr, flush=True)
         line["batched"] = batched_leg()
+        print("[bench] spring leg", file=sys.stderr, flush=True)
+        line["spring"] = spring_leg()
+        print("[bench] host-accumulation ablation", file=sys.stderr, flush=True)
+        line["host_accumulation_ablation"] = host_accumulation_leg()
+        gpu_path = sec.get(W.C2_PLAIN.name, {}).get("value")
+        if gpu_path:
+            line["host_accumulation_ablation"]["gpu_resident_evals_per_s"] = gpu_path
+            line["host_accumulation_ablation"]["gpu_resident_speedup"] = \
+                gpu_path / line["host_accumulation_ablation"]["evals_per_s"]
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w, edges, args.cpu_budget)

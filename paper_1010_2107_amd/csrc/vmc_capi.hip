@@ -612,7 +612,9 @@ int spring_generate(vmc_grid_t g, int integrand, const double* theta, int ntheta
   SP.max_events = static_cast<uint64_t>(max_events);
   SP.events = events;
   SP.event_trial = event_trial;
-  const size_t lds = static_cast<size_t>(ks->tab_entry_bytes) * g->d * g->N;
+  // grid table, then the staged points
+  const size_t lds = static_cast<size_t>(ks->tab_entry_bytes) * g->d * g->N +
+                     static_cast<size_t>(kStage) * g->d * (fp64 ? sizeof(double) : sizeof(float));
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(ks->spring, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return fail(VMC_E_NBINS, "dim x nbins needs %zu bytes of LDS per block: %s", lds,

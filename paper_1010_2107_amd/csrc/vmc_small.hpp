@@ -26,26 +26,26 @@ __global__ __launch_bounds__(kBlock) void k_publish(double* bins, double* stripe
                                                     double* scal, int fwd, int strat, int ngrad, double n, double kd,
                                                     double Md) {
   __shared__ double tot[kStripeScal];
+  // all kStripes loads of a slot are issued before any store
+  auto gather = [&](int slot) {
+    double c[kStripes];
+#pragma unroll
+    for (int s = 0; s < kStripes; ++s) c[s] = stripes[static_cast<size_t>(s) * stripe_len + slot];
+    double v = 0.0;
+#pragma unroll
+    for (int s = 0; s < kStripes; ++s) {
+      v += c[s];
+      stripes[static_cast<size_t>(s) * stripe_len + slot] = 0.0;
+    }
+    return v;
+  };
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i < nb) {
-    double v = 0.0;
-    for (int s = 0; s < kStripes; ++s) {
-      double* p = stripes + static_cast<size_t>(s) * stripe_len + i;
-      v += *p;
-      *p = 0.0;
-    }
+    const double v = gather(i);
     if (fwd) bins[i] = v;
   }
   if (blockIdx.x != 0) return;
-  if (threadIdx.x < kStripeScal) {
-    double v = 0.0;
-    for (int s = 0; s < kStripes; ++s) {
-      double* p = stripes + static_cast<size_t>(s) * stripe_len + nb + threadIdx.x;
-      v += *p;
-      *p = 0.0;
-    }
-    tot[threadIdx.x] = v;
-  }
+  if (threadIdx.x < kStripeScal) tot[threadIdx.x] = gather(nb + threadIdx.x);
   __syncthreads();
   if (threadIdx.x != 0) return;
   if (fwd) {

@@ -55,81 +55,123 @@ struct SpringArgs {
   uint64_t* event_trial;   // [max_events] trial number of each stored event, or NULL
 };
 
+// Kept events are staged in LDS and written out kStage at a time: one
+// atomic reserves a block's run of consecutive slots, and the copy to the
+// event buffer is contiguous.
+constexpr int kStage = 512;
+
 template <class F>
 __global__ __launch_bounds__(kBlock) void k_spring(const SpringArgs P) {
   using T = typename F::T;
   constexpr int D = F::D;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[(kBlock / kWave) * 2];
+  __shared__ uint64_t s_trial[kStage];
+  __shared__ unsigned int s_n;
+  __shared__ unsigned long long s_base;
   const SampleArgs& A = P.A;
   typename TabEntry<T>::type* tab;
   (void)setup_lds<F, 0>(A, smem, tab);
+  // staged points after the grid table
+  T* s_x = reinterpret_cast<T*>(smem + sizeof(typename TabEntry<T>::type) * D * A.nbins);
   const F fn = block_setup<F>(A.theta);
+  if (threadIdx.x == 0) s_n = 0u;
 
   const uint64_t total = P.state[SP_TOTAL];
   const double unit = __longlong_as_double(static_cast<long long>(P.state[SP_UNIT]));
   const uint32_t kbits = static_cast<uint32_t>(P.state[SP_KBITS]);
+  const uint32_t last = A.M - 1;
   const int lane = threadIdx.x & (kWave - 1);
   unsigned long long* slot_ctr = reinterpret_cast<unsigned long long*>(P.state + SP_SLOT);
   double n_kept = 0.0, n_over = 0.0;
 
+  // copy the staged events out (whole block; s_n is block-uniform here)
+  auto flush = [&]() {
+    const unsigned int n = s_n;
+    if (threadIdx.x == 0) s_base = atomicAdd(slot_ctr, static_cast<unsigned long long>(n));
+    __syncthreads();
+    const uint64_t base = s_base;
+    const uint64_t room = base < P.max_events ? P.max_events - base : 0;
+    const uint64_t m = min(static_cast<uint64_t>(n), room);
+    T* ev = static_cast<T*>(P.events) + base * D;
+    for (uint64_t k = threadIdx.x; k < m * D; k += kBlock) ev[k] = s_x[k];
+    if (P.event_trial)
+      for (uint64_t k = threadIdx.x; k < m; k += kBlock) P.event_trial[base + k] = s_trial[k];
+    __syncthreads();
+    if (threadIdx.x == 0) s_n = 0u;
+    __syncthreads();
+  };
+
+  __syncthreads();
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kBlock;
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < P.ntrials; i += stride) {
-    const uint64_t t = P.trial0 + i;
-    // words 0..D-1: the point in the cube; D, D+1: the cube choice (low and
-    // high half of r64); D+2: the acceptance uniform
-    uint32_t w[D + 3];
-    philox_words<D + 3>(static_cast<uint32_t>(t), kSpringTag, A.it, static_cast<uint32_t>(t >> 32), A.key, w);
-    const uint64_t r64 = (static_cast<uint64_t>(w[D + 1]) << 32) | w[D];
-    const uint64_t r = __umul64hi(r64, total);
-    const uint64_t b = kbits ? (r64 >> (64 - kbits)) : 0;
-    uint32_t lo = P.guide[b], hi = P.guide[b + 1];
-    while (lo < hi) {  // last c in [lo, hi] with P_c <= r
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (P.prefix[mid] <= r)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    const uint32_t c = lo;
-    const double g = static_cast<double>(P.prefix[c + 1] - P.prefix[c]) * unit;
-    uint32_t cc[D], wp[D];
-    {
-      uint32_t rem = c;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const uint32_t q = rem / A.ng;
-        cc[a] = rem - q * A.ng;
-        rem = q;
-        wp[a] = w[a];
+  for (uint64_t base_i = static_cast<uint64_t>(blockIdx.x) * kBlock; base_i < P.ntrials; base_i += stride) {
+    const uint64_t i = base_i + threadIdx.x;
+    bool keep = false;
+    T x[D];
+    uint64_t t = 0;
+    if (i < P.ntrials) {
+      t = P.trial0 + i;
+      // words 0..D-1: the point in the cube; D, D+1: the cube choice (low
+      // and high half of r64); D+2: the acceptance uniform
+      uint32_t w[D + 3];
+      philox_words<D + 3>(static_cast<uint32_t>(t), kSpringTag, A.it, static_cast<uint32_t>(t >> 32), A.key, w);
+      const uint64_t r64 = (static_cast<uint64_t>(w[D + 1]) << 32) | w[D];
+      const uint64_t r = __umul64hi(r64, total);
+      const uint64_t b = kbits ? (r64 >> (64 - kbits)) : 0;
+      uint32_t lo = min(P.guide[b], last), hi = min(P.guide[b + 1], last);
+      while (lo < hi) {  // last c in [lo, hi] with P_c <= r
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (P.prefix[mid] <= r)
+          lo = mid;
+        else
+          hi = mid - 1;
       }
+      const uint32_t c = lo;
+      const double g = static_cast<double>(P.prefix[c + 1] - P.prefix[c]) * unit;
+      uint32_t cc[D], wp[D];
+      {
+        uint32_t rem = c;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const uint32_t q = rem / A.ng;
+          cc[a] = rem - q * A.ng;
+          rem = q;
+          wp[a] = w[a];
+        }
+      }
+      int j[D];
+      T jac;
+      make_point<T, D, true>(A, tab, wp, cc, j, x, jac);
+      T gr[F::NGRAD + 1];
+      const T fv = fn.template eval<false>(x, gr);
+      const double wd = static_cast<double>(fv * jac);
+      const double u = static_cast<double>(((w[D + 2] >> 9) << 1) | 1u) * 5.9604644775390625e-08;
+      keep = u * g < wd;
+      n_kept += keep ? 1.0 : 0.0;
+      n_over += (wd > g) ? 1.0 : 0.0;
     }
-    int j[D];
-    T x[D], jac;
-    make_point<T, D, true>(A, tab, wp, cc, j, x, jac);
-    T gr[F::NGRAD + 1];
-    const T fv = fn.template eval<false>(x, gr);
-    const double wd = static_cast<double>(fv * jac);
-    const double u = static_cast<double>(((w[D + 2] >> 9) << 1) | 1u) * 5.9604644775390625e-08;
-    const bool keep = u * g < wd;
-    n_kept += keep ? 1.0 : 0.0;
-    n_over += (wd > g) ? 1.0 : 0.0;
-    // one slot counter update per wave: the kept lanes take consecutive slots
+    // stage: one LDS atomic per wave, kept lanes take consecutive entries
+    // (at most kBlock new entries: the stage was flushed below kStage - kBlock)
     const uint64_t mask = __ballot(keep);
     if (keep) {
       const int leader = __ffsll(static_cast<unsigned long long>(mask)) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(slot_ctr, static_cast<unsigned long long>(__popcll(mask)));
-      base = __shfl(base, leader, kWave);
-      const uint64_t slot = base + __popcll(mask & __lanemask_lt());
-      if (slot < P.max_events) {
-        T* ev = static_cast<T*>(P.events) + slot * D;
+      unsigned int wbase = 0;
+      if (lane == leader) wbase = atomicAdd(&s_n, static_cast<unsigned int>(__popcll(mask)));
+      wbase = __shfl(wbase, leader, kWave);
+      const unsigned int e = wbase + static_cast<unsigned int>(__popcll(mask & __lanemask_lt()));
 #pragma unroll
-        for (int a = 0; a < D; ++a) ev[a] = x[a];
-        if (P.event_trial) P.event_trial[slot] = t;
-      }
+      for (int a = 0; a < D; ++a) s_x[e * D + a] = x[a];
+      s_trial[e] = t;
     }
+    __syncthreads();
+    const unsigned int staged = s_n;
+    __syncthreads();  // every thread has read the count before the next stage
+    if (staged > static_cast<unsigned int>(kStage - kBlock)) flush();
   }
+  __syncthreads();
+  const unsigned int staged = s_n;
+  __syncthreads();
+  if (staged > 0u) flush();
   // counts (exact in FP64 below 2^53): one atomic per block and counter
   const double wk = wave_sum(n_kept), wo = wave_sum(n_over);
   if (lane == 0) {

@@ -138,6 +138,18 @@ class Grid:
         assert e.shape == (self.dim, self.nbins + 1)
         L.call("vmc_set_edges", self._h, e.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream))
 
+    def dump_into(self, integrand, theta, ncall, seed, it, s0, words=None, w=None, f=None, jac=None, stream=None):
+        """Per-sample dump into caller tensors (device; any may be None):
+        words [count][dim] int32, w / f / jac [count] float32 or float64
+        (float64 selects the FP64 instantiation)."""
+        outs = [t for t in (words, w, f, jac) if t is not None]
+        count = outs[0].shape[0] if outs else 0
+        fp64 = any(t.dtype == torch.float64 for t in (w, f, jac) if t is not None)
+        th = self.theta_tensor(theta)
+        L.call("vmc_dump_samples", self._h, int(integrand), _ptr(th if th.numel() else None), th.numel(),
+               int(ncall), int(seed), int(it), L.FLAG_FP64 if fp64 else 0, int(s0), int(count), _ptr(words),
+               _ptr(w), _ptr(f), _ptr(jac), _stream_ptr(stream))
+
     def dump(self, integrand, theta, ncall, seed, it, s0, count, fp64=False, stream=None):
         """Per-sample words, w = f J, f and J of samples [s0, s0+count)."""
         dt = torch.float64 if fp64 else torch.float32
