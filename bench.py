@@ -401,13 +401,18 @@ def main(argv=None):
             line[key] = m[key]
     if not args.no_secondary:
         sec = {}
-        for w2 in (W.C2, W.C2_PLAIN, W.C3):
+        for w2 in (W.C2, W.C2_PLAIN, W.C3, W.C6):
             if w2.name == w.name:
                 continue
             g2 = Grid(w2.dim, w2.nbins)
             m2 = measure_workload(g2, w2, w2.itmx + w2.itmx2, 1)
             r2 = m2["res"]
             z2 = None if w2.I_ref is None else abs(r2["Ibar"] - w2.I_ref) / r2["sigbar"]
+            if w2.integrand == W.WHEL:
+                p = os.path.join(ROOT, "tests", "golden", "whel_reference.json")
+                ref = json.load(open(p)).get(str(w2.dim)) if os.path.exists(p) else None
+                if ref:
+                    z2 = abs(r2["Ibar"] - ref["Ibar"]) / math.hypot(r2["sigbar"], ref["sigbar"])
             sec[w2.name] = {k: m2[k] for k in ("value", "fwd_adj_evals_per_s", "fused_evals_per_s") if k in m2}
             sec[w2.name].update({"Ibar": r2["Ibar"], "sigbar": r2["sigbar"], "z": z2,
                                  "kernel_ms_per_launch": m2["kms"] / max(m2["nl"], 1)})

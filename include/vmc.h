@@ -67,6 +67,11 @@ extern "C" {
                          /* etamax, dRmin); gradients w.r.t. (M, Gamma, g)    */
 #define VMC_PSVOL 6      /* PDF x massless phase-space weight of VMC_WJETS    */
                          /* without cuts or |M|^2; theta (sqrtS, pTmin)       */
+#define VMC_WHEL 7       /* u dbar -> W+(-> mu+ nu) + n gluons (Sec. 5, eq. 1)*/
+                         /* from helicity amplitudes, n = 0..2, d = 3n + 5   */
+                         /* (last variable: gluon helicities); theta (M,     */
+                         /* Gamma, g_s, sqrtS, pTmin, etamax_mu, etamax_g,    */
+                         /* pTij_min); gradients w.r.t. (M, Gamma, g_s)       */
 
 /* iterate flags */
 #define VMC_FLAG_FP64 1u /* evaluate map and integrand in double precision   */

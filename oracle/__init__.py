@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-CONST, LINEAR, GAUSS, DGAUSS, GAUSS_AXES, WJETS, PSVOL = range(7)
+CONST, LINEAR, GAUSS, DGAUSS, GAUSS_AXES, WJETS, PSVOL, WHEL = range(8)
 
 _lib = None
 
@@ -219,6 +219,29 @@ def wjets_event(x, theta, want_grad=False):
 
 
 # ------------------------------------------------------------ iteration
+def whel_event(x, theta, want_grad=False):
+    """u dbar -> W+(-> mu+ nu) + n gluons at one point: f, momenta (g..,
+    mu, nu; partonic frame), aux (x1, x2, shat, Jx, lum, Vn, m_munu^2,
+    pass) and, if asked, the gradient w.r.t. (M, Gamma, g_s)."""
+    xx = _d(x)
+    th = _d(theta)
+    d = xx.size
+    n = (d - 5) // 3
+    p = np.zeros(4 * (n + 2))
+    aux = np.zeros(8)
+    g = np.zeros(3)
+    L = lib()
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.orc_whel_event.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, dp]
+    L.orc_whel_event.restype = ctypes.c_double
+    f = L.orc_whel_event(d, _ptr(xx, ctypes.c_double), _ptr(th, ctypes.c_double), th.size,
+                         _ptr(p, ctypes.c_double), _ptr(aux, ctypes.c_double), _ptr(g, ctypes.c_double))
+    out = dict(f=f, p=p.reshape(n + 2, 4), aux=aux)
+    if want_grad:
+        out["grad"] = g
+    return out
+
+
 def uniform_edges(d, nbins):
     return np.tile(np.arange(nbins + 1, dtype=np.float64) / nbins, (d, 1))
 

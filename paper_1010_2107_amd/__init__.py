@@ -5,10 +5,10 @@ with this thin Python binding (ctypes + torch device memory and streams).
 The HIP library is loaded on first use; if it is missing or cannot be
 loaded every call raises VmcNotBuilt -- there is no CPU fallback.
 """
-from ._lib import (CONST, DGAUSS, FLAG_FP64, GAUSS, GAUSS_AXES, LINEAR, PSVOL, WJETS, VmcError, VmcNotBuilt,
-                   header_functions, lib)
+from ._lib import (CONST, DGAUSS, FLAG_FP64, GAUSS, GAUSS_AXES, LINEAR, PSVOL, WHEL, WJETS, VmcError,
+                   VmcNotBuilt, header_functions, lib)
 
-__all__ = ["CONST", "LINEAR", "GAUSS", "DGAUSS", "GAUSS_AXES", "WJETS", "PSVOL", "FLAG_FP64", "VmcError",
+__all__ = ["CONST", "LINEAR", "GAUSS", "DGAUSS", "GAUSS_AXES", "WJETS", "PSVOL", "WHEL", "FLAG_FP64", "VmcError",
            "VmcNotBuilt", "lib", "header_functions", "Grid", "integrate"]
 
 

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libvmc.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "vmc.h")
 
 # integrand ids and flags (include/vmc.h)
-CONST, LINEAR, GAUSS, DGAUSS, GAUSS_AXES, WJETS, PSVOL = range(7)
+CONST, LINEAR, GAUSS, DGAUSS, GAUSS_AXES, WJETS, PSVOL, WHEL = range(8)
 FLAG_FP64 = 1
 
 S_S1, S_S2, S_V, S_NONFINITE, S_I, S_VAR, S_NEFF, S_NZERO = 0, 1, 2, 3, 4, 5, 6, 7

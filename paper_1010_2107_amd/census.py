@@ -88,6 +88,45 @@ def wjets(n_p: int) -> Census:
     return Census(int(round(f)), int(round(f_fail)), int(t), int(t_fail))
 
 
+def whel(n: int) -> Census:
+    """u dbar -> W + n gluons (helicity amplitudes), per the HIP source:
+    complex multiply = 6 flops (4 mul, 2 add), complex add = 2."""
+    nf = n + 2
+    D = 3 * n + 5
+    f = t = 0
+    f += MAP_PER_AXIS * D
+    f += 17
+    t += 4
+    for K in range(nf - 2, 0, -1):  # mass chain
+        ff, tt = _newton_branch_avg(K)
+        f += ff + 1
+        t += tt + 1
+    f += 17 + (nf - 2) * 52  # two-body steps and boosts
+    t += 3 + (nf - 2) * 5
+    f += 8 * (n + 1)  # light-cone components, pT, rapidity of the gluons and the muon
+    t += 4 * (n + 1)
+    if n == 2:
+        f += 12  # Durham pT_ij between the two gluons
+        t += 3
+    f_fail, t_fail = f + 1, t
+    SBAR, TOP, PROP, SBAR_U = 36, 18, 35, 4
+    f += 2 * 12 + 40  # lepton spinors and current
+    t += 2
+    if n == 0:
+        f += TOP + 3
+    elif n == 1:
+        f += 15 + (SBAR_U + PROP + TOP) + (SBAR_U + PROP + TOP) + 4
+        t += 3 + 2
+    else:
+        f += 2 * 15 + 60  # polarisations, three-gluon current
+        f += 3 * (SBAR_U + PROP)  # shared prefixes
+        f += 6 * (SBAR + PROP + TOP) + (SBAR_U + PROP + TOP + TOP) + 20 + 10
+        t += 2 * 3 + 1 + 9
+    f += 8  # W propagator, prefactor
+    t += 1
+    return Census(int(round(f)), int(round(f_fail)), int(t), int(t_fail))
+
+
 def gaussian(integrand: int, d: int) -> Census:
     if integrand == W.GAUSS or integrand == W.GAUSS_AXES:
         fl = MAP_PER_AXIS * d + 3 * d + 2 + 1
@@ -103,4 +142,6 @@ def gaussian(integrand: int, d: int) -> Census:
 def for_workload(w) -> Census:
     if w.integrand == W.WJETS:
         return wjets((w.dim - 4) // 3)
+    if w.integrand == W.WHEL:
+        return whel((w.dim - 5) // 3)
     return gaussian(w.integrand, w.dim)

@@ -201,7 +201,7 @@ int plan_launch(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
                 uint32_t it, uint32_t flags, Plan& P) {
   int rc = need_bound(g);
   if (rc) return rc;
-  if (integrand < VMC_CONST || integrand > VMC_PSVOL)
+  if (integrand < VMC_CONST || integrand > VMC_WHEL)
     return fail(VMC_E_INTEGRAND, "unknown integrand id %d", integrand);
   const bool fp64 = flags & VMC_FLAG_FP64;
   P.ks = lookup_kernels(integrand, g->d, fp64);
@@ -576,7 +576,7 @@ int spring_generate(vmc_grid_t g, int integrand, const double* theta, int ntheta
   if (rc) return rc;
   if (!prefix || prefix != g->sp_prefix || guide != g->sp_guide || state != g->sp_state || g->sp_ng != g->ng)
     return fail(VMC_E_SPRING, "these buffers have not been set up by spring_setup for this stratification");
-  if (integrand < VMC_CONST || integrand > VMC_PSVOL) return fail(VMC_E_INTEGRAND, "unknown integrand id %d", integrand);
+  if (integrand < VMC_CONST || integrand > VMC_WHEL) return fail(VMC_E_INTEGRAND, "unknown integrand id %d", integrand);
   const bool fp64 = flags & VMC_FLAG_FP64;
   const KernelSet* ks = lookup_kernels(integrand, g->d, fp64);
   if (!ks)

@@ -153,6 +153,87 @@ __device__ __forceinline__ int ilogb_(double x) { return __builtin_amdgcn_frexp_
 __device__ __forceinline__ float ldexp_(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
 __device__ __forceinline__ double ldexp_(double x, int e) { return __builtin_amdgcn_ldexp(x, e); }
 
+// RAMBO on diet (Plaetzer, arXiv:1308.2922): NOUT massless momenta in the
+// rest frame of a system of mass rs from x[X0 .. X0 + 3 NOUT - 5]: first
+// the masses M_2 > ... > M_{NOUT-1} (x[X0 + i - 2] fixes M_i), then one
+// direction (cos theta, phi) per two-body step i = 1..NOUT-1, each boosted
+// by the current Q_i.  Mi[1..NOUT] and Ui[i] = 1 - M_i^2 / M_{i-1}^2 are
+// returned with the momenta p[0..NOUT-1].
+template <int NOUT, int X0, int I, typename T, int D>
+__device__ __forceinline__ void mass_chain(const T (&x)[D], T (&Mi)[NOUT + 1], T (&Ui)[NOUT + 1]) {
+  if constexpr (I <= NOUT - 1) {
+    const TU<T> tu = mass_fraction<NOUT - I, T>(x[X0 + I - 2]);
+    Mi[I] = Mi[I - 1] * vsqrt(tu.t);
+    Ui[I] = tu.u;
+    mass_chain<NOUT, X0, I + 1>(x, Mi, Ui);
+  }
+}
+
+template <int NOUT, int X0, typename T, int D>
+__device__ __forceinline__ void rambo_diet(const T (&x)[D], T rs, T (&Mi)[NOUT + 1], T (&Ui)[NOUT + 1],
+                                           T (&p)[NOUT][4]) {
+  Mi[1] = rs;
+  Ui[1] = T(0);
+  mass_chain<NOUT, X0, 2>(x, Mi, Ui);
+  Mi[NOUT] = T(0);
+  Ui[NOUT] = T(1);
+  T Q[4] = {rs, T(0), T(0), T(0)};
+#pragma unroll
+  for (int i = 1; i <= NOUT - 1; ++i) {
+    const T q = T(0.5) * Mi[i] * Ui[i + 1];  // (M_i^2 - M_{i+1}^2) / (2 M_i)
+    const T rc = x[X0 + NOUT - 2 + 2 * i - 2];
+    const T rp = x[X0 + NOUT - 2 + 2 * i - 1];
+    const T cth = fma(T(2), rc, T(-1));
+    const T sth = T(2) * vsqrt(rc * (T(1) - rc));
+    T sp, cp;
+    vsincos2pi(rp, sp, cp);
+    const T nx = sth * cp, ny = sth * sp, nz = cth;
+    const T pr[4] = {q, q * nx, q * ny, q * nz};
+    const T qr[4] = {Mi[i] - q, -q * nx, -q * ny, -q * nz};
+    if (i == 1) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        p[0][c] = pr[c];
+        Q[c] = qr[c];
+      }
+    } else {
+      const T iM = vrcp(Mi[i]);
+      const T iEM = vrcp(Q[0] + Mi[i]);
+      T qn[4];
+      boost(Q, iM, iEM, pr, p[i - 1]);
+      boost(Q, iM, iEM, qr, qn);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Q[c] = qn[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) p[NOUT - 1][c] = Q[c];
+}
+
+// Massless light-cone components E +- pz, rapidity and pT of a momentum:
+// the larger component directly, the smaller as pT^2 / larger; rapidity =
+// +-ln(larger / pT).
+template <typename T>
+struct LightCone {
+  T pt2, pt, rpt2, lp, lm, eta;
+};
+template <typename T>
+__device__ __forceinline__ LightCone<T> light_cone(const T (&v)[4]) {
+  LightCone<T> r;
+  r.pt2 = v[1] * v[1] + v[2] * v[2];
+  const T e = v[0], z = v[3];
+  const T big = e + fabs(z);
+  const T small = r.pt2 * vrcp(big);
+  const T rpt = vrsqrt(r.pt2);
+  const T ya = vlog_fast(big * rpt);
+  r.lp = z > T(0) ? big : small;
+  r.lm = z > T(0) ? small : big;
+  r.eta = z > T(0) ? ya : -ya;
+  r.pt = r.pt2 * rpt;
+  r.rpt2 = rpt * rpt;
+  return r;
+}
+
 template <typename TT, int NP, bool FULL>
 struct WJetsF {
   using T = TT;
@@ -220,44 +301,8 @@ struct WJetsF {
       const T yb = T(0.5) * (la - lb);
       // ---- RAMBO on diet: masses M_1 = sqrt(s) > M_2 > ... > M_{n-1} > M_n = 0
       T Mi[NOUT + 1], Ui[NOUT + 1];
-      Mi[1] = rs;
-      Ui[1] = T(0);
-      mass_chain<2>(x, Mi, Ui);
-      Mi[NOUT] = T(0);
-      Ui[NOUT] = T(1);
-      // ---- two-body steps, each boosted by the current Q_i
       T p[NOUT][4];
-      T Q[4] = {rs, T(0), T(0), T(0)};
-#pragma unroll
-      for (int i = 1; i <= NOUT - 1; ++i) {
-        const T q = T(0.5) * Mi[i] * Ui[i + 1];  // (M_i^2 - M_{i+1}^2) / (2 M_i)
-        const T rc = x[NOUT + 2 * i - 2];
-        const T rp = x[NOUT + 2 * i - 1];
-        const T cth = fma(T(2), rc, T(-1));
-        const T sth = T(2) * vsqrt(rc * (T(1) - rc));
-        T sp, cp;
-        vsincos2pi(rp, sp, cp);
-        const T nx = sth * cp, ny = sth * sp, nz = cth;
-        const T pr[4] = {q, q * nx, q * ny, q * nz};
-        const T qr[4] = {Mi[i] - q, -q * nx, -q * ny, -q * nz};
-        if (i == 1) {
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            p[0][c] = pr[c];
-            Q[c] = qr[c];
-          }
-        } else {
-          const T iM = vrcp(Mi[i]);
-          const T iEM = vrcp(Q[0] + Mi[i]);
-          T qn[4];
-          boost(Q, iM, iEM, pr, p[i - 1]);
-          boost(Q, iM, iEM, qr, qn);
-#pragma unroll
-          for (int c = 0; c < 4; ++c) Q[c] = qn[c];
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < 4; ++c) p[NOUT - 1][c] = Q[c];
+      rambo_diet<NOUT, 2>(x, rs, Mi, Ui, p);
 
       // ---- visible particles: partons 0..NP-1 and the electron NP
       constexpr int NV = NP + 1;
@@ -265,19 +310,13 @@ struct WJetsF {
       bool pass = true;
 #pragma unroll
       for (int j = 0; j < NV; ++j) {
-        pt2[j] = p[j][1] * p[j][1] + p[j][2] * p[j][2];
-        const T e = p[j][0], z = p[j][3];
-        // light-cone components E +- pz: the larger directly, the smaller as
-        // pT^2 / larger (massless); rapidity = +-ln(larger / pT)
-        const T big = e + fabs(z);
-        const T small = pt2[j] * vrcp(big);
-        const T rpt = vrsqrt(pt2[j]);
-        const T ya = vlog_fast(big * rpt);
-        lp[j] = z > T(0) ? big : small;
-        lm[j] = z > T(0) ? small : big;
-        eta[j] = z > T(0) ? ya : -ya;
-        pt[j] = pt2[j] * rpt;
-        rpt2[j] = rpt * rpt;
+        const LightCone<T> lc = light_cone(p[j]);
+        pt2[j] = lc.pt2;
+        pt[j] = lc.pt;
+        rpt2[j] = lc.rpt2;
+        lp[j] = lc.lp;
+        lm[j] = lc.lm;
+        eta[j] = lc.eta;
         pass = pass && (pt2[j] > ptmin2) && (fabs(eta[j] + yb) < etamax);
       }
       // Delta R > R: either Delta eta^2 >= R^2, or cos(Delta phi) < cos(phi0)
@@ -351,16 +390,6 @@ struct WJetsF {
     }
   }
 
-  // M_i and U_i = 1 - M_i^2 / M_{i-1}^2 for i = I..n-1 from x[2..n-1]
-  template <int I>
-  __device__ __forceinline__ void mass_chain(const T (&x)[D], T (&Mi)[NOUT + 1], T (&Ui)[NOUT + 1]) const {
-    if constexpr (I <= NOUT - 1) {
-      const TU<T> tu = mass_fraction<NOUT - I, T>(x[I]);
-      Mi[I] = Mi[I - 1] * vsqrt(tu.t);
-      Ui[I] = tu.u;
-      mass_chain<I + 1>(x, Mi, Ui);
-    }
-  }
 };
 
 template <typename T, int D>

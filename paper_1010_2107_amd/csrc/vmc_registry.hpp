@@ -45,8 +45,11 @@ const KernelSet* lookup_axes_f32(int id, int d);
 const KernelSet* lookup_gauss_f64(int id, int d);
 const KernelSet* lookup_phys_f32(int id, int d);
 const KernelSet* lookup_phys_f64(int id, int d);
+const KernelSet* lookup_whel_f32(int d);
+const KernelSet* lookup_whel_f64(int d);
 
 inline const KernelSet* lookup_kernels(int id, int d, bool fp64) {
+  if (id == 7) return fp64 ? lookup_whel_f64(d) : lookup_whel_f32(d);
   if (fp64) {
     if (id == 5 || id == 6) return lookup_phys_f64(id, d);
     return lookup_gauss_f64(id, d);

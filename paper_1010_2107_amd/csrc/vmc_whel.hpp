@@ -1,0 +1,291 @@
+// vmc_whel.hpp -- the paper's process, u dbar -> W+(-> mu+ nu) + NG gluons
+// (Kanzaki, arXiv:1010.2107, Sec. 5, eq. 1; Table 4: 1, 2 and 8 Feynman
+// diagrams for NG = 0, 1, 2), from tree-level helicity amplitudes.
+//
+//   x0, x1          -> parton fractions and flux as for the W + partons toy
+//                      (toy PDF F(x) = x^-1.5 (1-x)^3 for u and dbar);
+//   x2..x_{3NG+3}   -> RAMBO on diet for g_1..g_NG, mu+, nu (so m_munu is
+//                      the last mass of the chain);
+//   x_{3NG+4}       -> the gluon helicities: one of the 2^NG configurations,
+//                      weight 2^NG (quark and lepton helicities are fixed by
+//                      the left-handed W coupling; the others vanish);
+//   cuts            -> gluons pT > pTmin, |eta| < eta_g, Durham
+//                      min(pT_i, pT_j) Delta R_ij > pTij between gluons; the
+//                      muon pT > pTmin, |eta| < eta_mu; eta in the pp frame;
+//   |M|^2           -> massless left-handed quark and lepton lines as chains
+//                      of 2x2 blocks on Weyl spinors (vertex V: V.sigmabar,
+//                      propagator P: P.sigma / P^2), colour-ordered
+//                      amplitudes summed with the colour matrix; Feynman
+//                      gauge, fixed g_W^2 = 4 sqrt2 G_F (80.4 GeV)^2;
+//   f               -> flux x Jacobian x V_n(s) / (2 s) x (1/36) x 2^NG x |M|^2.
+// theta = (M_W, Gamma_W, g_s, sqrtS, pTmin, eta_mu, eta_g, pTij); gradients
+// with respect to the first three.
+#pragma once
+
+#include "vmc_phys.hpp"
+
+namespace vmc {
+
+template <typename T>
+struct Cx {
+  T r, i;
+};
+template <typename T>
+__device__ __forceinline__ Cx<T> operator+(Cx<T> a, Cx<T> b) {
+  return {a.r + b.r, a.i + b.i};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> operator-(Cx<T> a, Cx<T> b) {
+  return {a.r - b.r, a.i - b.i};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> operator*(Cx<T> a, Cx<T> b) {
+  return {fma(a.r, b.r, -a.i * b.i), fma(a.r, b.i, a.i * b.r)};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> operator*(T s, Cx<T> a) {
+  return {s * a.r, s * a.i};
+}
+template <typename T>
+__device__ __forceinline__ T norm2(Cx<T> a) {
+  return fma(a.r, a.r, a.i * a.i);
+}
+
+template <typename T>
+struct Sp {  // a 2-component spinor
+  Cx<T> a, b;
+};
+template <typename T>
+struct CV {  // a complex contravariant four-vector
+  Cx<T> v[4];
+};
+
+// (V . sigmabar) x = [[V0+V3, V1 - i V2], [V1 + i V2, V0-V3]] x
+template <typename T>
+__device__ __forceinline__ Sp<T> sbar(const CV<T>& V, const Sp<T>& x) {
+  const Cx<T> p = V.v[0] + V.v[3], m = V.v[0] - V.v[3];
+  const Cx<T> lo = {V.v[1].r + V.v[2].i, V.v[1].i - V.v[2].r};  // V1 - i V2
+  const Cx<T> hi = {V.v[1].r - V.v[2].i, V.v[1].i + V.v[2].r};  // V1 + i V2
+  return {p * x.a + lo * x.b, hi * x.a + m * x.b};
+}
+// first component only (the last vertex before v_L(p_dbar) = (r, 0))
+template <typename T>
+__device__ __forceinline__ Cx<T> sbar_top(const CV<T>& V, const Sp<T>& x) {
+  const Cx<T> p = V.v[0] + V.v[3];
+  const Cx<T> lo = {V.v[1].r + V.v[2].i, V.v[1].i - V.v[2].r};
+  return p * x.a + lo * x.b;
+}
+// (V . sigmabar) (0, 1): the first vertex on u_L(p_u) = (0, r)
+template <typename T>
+__device__ __forceinline__ Sp<T> sbar_u(const CV<T>& V) {
+  return {{V.v[1].r + V.v[2].i, V.v[1].i - V.v[2].r}, V.v[0] - V.v[3]};
+}
+// propagator (P . sigma) x / P^2 for a real momentum P
+template <typename T>
+__device__ __forceinline__ Sp<T> prop(const T (&P)[4], const Sp<T>& x) {
+  const T inv = vrcp(fma(P[0], P[0], -fma(P[1], P[1], fma(P[2], P[2], P[3] * P[3]))));
+  const T m = (P[0] - P[3]) * inv, p = (P[0] + P[3]) * inv;
+  const Cx<T> lo = {-P[1] * inv, P[2] * inv};   // -(P1 - i P2) / P^2
+  const Cx<T> hi = {-P[1] * inv, -P[2] * inv};  // -(P1 + i P2) / P^2
+  return {m * x.a + lo * x.b, hi * x.a + p * x.b};
+}
+
+// left-chirality spinor of a massless momentum (p.sigmabar u = 0, |u|^2 = 2E)
+template <typename T>
+__device__ __forceinline__ Sp<T> weyl(const T (&p)[4]) {
+  const T pp = p[0] + p[3], pm = p[0] - p[3];
+  if (pp >= pm) {
+    const T r = vrsqrt(pp);
+    return {{-p[1] * r, p[2] * r}, {pp * r, T(0)}};
+  }
+  const T r = vrsqrt(pm);
+  return {{pm * r, T(0)}, {-p[1] * r, -p[2] * r}};
+}
+
+template <typename TT, int NG>
+struct WHelF {
+  using T = TT;
+  static constexpr int NOUT = NG + 2;  // g_1..g_NG, mu+, nu
+  static constexpr int D = 3 * NG + 5;
+  static constexpr int NGRAD = 3;
+  static constexpr int NTHETA = 8;
+
+  T L, LL, sqrtS, pre, ptmin2, eta_mu, eta_g, ptij2;
+  T M, Mv2, M2G2, twoMG2, m2M2G, two_ng_over_g;
+
+  __device__ void setup(const double* th) {
+    const double pi = 3.14159265358979323846;
+    const double Md = th[0], Gd = th[1], gs = th[2], sS = th[3], ptm = th[4];
+    const double S = sS * sS;
+    const double tau0 = ((1.0 + NG) * ptm) * ((1.0 + NG) * ptm) / S;
+    const double Ld = log(tau0);
+    const double cV = pow(2.0 * pi, 4.0 - 3.0 * NOUT) * pow(pi / 2.0, NOUT - 1) /
+                      (static_cast<double>(factorial(NOUT - 1)) * factorial(NOUT - 2));
+    const double gw2 = 4.0 * sqrt(2.0) * 1.1663787e-5 * 80.4 * 80.4;
+    // f = flux Jx cV s^(n-2) / (2 s) (2^NG / 36) g_s^(2NG) (g_W^2/2)^2 |A|^2 / |D|^2,
+    // |A|^2 = s |chain|^2 (the spinors of p_u and p_dbar contribute sqrt(s) each)
+    pre = static_cast<T>(cV * 0.5 * (1 << NG) / 36.0 * pow(gs, 2.0 * NG) * gw2 * gw2 / 4.0);
+    L = static_cast<T>(Ld);
+    LL = static_cast<T>(Ld * Ld);
+    sqrtS = static_cast<T>(sS);
+    ptmin2 = static_cast<T>(ptm * ptm);
+    eta_mu = static_cast<T>(th[5]);
+    eta_g = static_cast<T>(th[6]);
+    ptij2 = static_cast<T>(th[7] * th[7]);
+    M = static_cast<T>(Md);
+    Mv2 = static_cast<T>(Md * Md);
+    M2G2 = static_cast<T>(Md * Md * Gd * Gd);
+    twoMG2 = static_cast<T>(2.0 * Md * Gd * Gd);
+    m2M2G = static_cast<T>(-2.0 * Md * Md * Gd);
+    two_ng_over_g = static_cast<T>(2.0 * NG / gs);
+  }
+
+  // outgoing gluon k, helicity lam: conj of (0, (-lam e1 - i e2) / sqrt2),
+  // e1, e2 the polar and azimuthal unit vectors of k
+  __device__ __forceinline__ static CV<T> eps_out(const T (&k)[4], T pt, T lam) {
+    const T s = T(0.70710678118654752440);
+    const T ik = vrcp(k[0]), ip = vrcp(pt);
+    const T e1x = k[3] * k[1] * ik * ip, e1y = k[3] * k[2] * ik * ip, e1z = -pt * ik;
+    const T e2x = -k[2] * ip, e2y = k[1] * ip;
+    const T a = -lam * s;
+    CV<T> e;
+    e.v[0] = {T(0), T(0)};
+    e.v[1] = {a * e1x, s * e2x};
+    e.v[2] = {a * e1y, s * e2y};
+    e.v[3] = {a * e1z, T(0)};
+    return e;
+  }
+
+  template <bool GRAD>
+  __device__ __forceinline__ T eval(const T (&x)[D], T (&g)[NGRAD + 1]) const {
+    const T la = L * (T(1) - x[0]);
+    const T lb = L * x[0] * (T(1) - x[1]);
+    const T h = vexp(T(0.5) * (la + lb));  // sqrt(tau)
+    const T rs = sqrtS * h;
+    const T shat = rs * rs;
+    const T om = vexpm1(la) * vexpm1(lb);
+    const T fluxjac = LL * x[0] * (om * om * om) * vrcp(h);
+    const T yb = T(0.5) * (la - lb);
+    T Mi[NOUT + 1], Ui[NOUT + 1];
+    T p[NOUT][4];
+    rambo_diet<NOUT, 2>(x, rs, Mi, Ui, p);
+    if (GRAD) g[0] = g[1] = g[2] = T(0);
+
+    // ---- cuts: gluons 0..NG-1, the muon NG
+    bool pass = true;
+    T pt[NG + 1], pt2[NG + 1], eta[NG + 1];
+#pragma unroll
+    for (int j = 0; j <= NG; ++j) {
+      const LightCone<T> lc = light_cone(p[j]);
+      pt[j] = lc.pt;
+      pt2[j] = lc.pt2;
+      eta[j] = lc.eta;
+      pass = pass && (lc.pt2 > ptmin2) && (fabs(lc.eta + yb) < (j < NG ? eta_g : eta_mu));
+    }
+    if constexpr (NG == 2) {
+      // min(pT_i, pT_j)^2 (Delta eta^2 + Delta phi^2) > pTij^2: with
+      // z = pTij^2 / min pT^2 - Delta eta^2, pass when z <= 0, else when
+      // Delta phi > sqrt z, i.e. cos Delta phi < cos sqrt z (z < pi^2)
+      const T de = eta[0] - eta[1];
+      const T z = ptij2 * vrcp(fmin(pt2[0], pt2[1])) - de * de;
+      const T dot = p[0][1] * p[1][1] + p[0][2] * p[1][2];
+      T cz;
+      if constexpr (sizeof(T) == 8) {
+        cz = cos(sqrt(fmax(z, T(0))));
+      } else {
+        T sz;
+        vsincos2pi(vsqrt(fmax(z, T(0))) * T(0.15915494309189535), sz, cz);
+      }
+      pass = pass && ((z <= T(0)) || (z < T(9.869604401089358) && dot < cz * pt[0] * pt[1]));
+    }
+    if (!pass) return T(0);
+
+    // ---- helicity configuration of the gluons
+    int hel = static_cast<int>(x[D - 1] * T(1 << NG));
+    hel = hel < (1 << NG) - 1 ? hel : (1 << NG) - 1;
+
+    // ---- lepton current L = u_L(nu)^dagger sigmabar v_L(mu), sigmabar = (1, -sigma)
+    const Sp<T> a = weyl(p[NOUT - 1]);
+    const Sp<T> b = weyl(p[NOUT - 2]);
+    const Cx<T> ac0 = {a.a.r, -a.a.i}, ac1 = {a.b.r, -a.b.i};
+    const Cx<T> a0b0 = ac0 * b.a, a0b1 = ac0 * b.b, a1b0 = ac1 * b.a, a1b1 = ac1 * b.b;
+    CV<T> Lc;
+    Lc.v[0] = a0b0 + a1b1;
+    Lc.v[1] = {-(a0b1.r + a1b0.r), -(a0b1.i + a1b0.i)};
+    Lc.v[2] = {-(a0b1.i - a1b0.i), a0b1.r - a1b0.r};  // i (a0* b1 - a1* b0)
+    Lc.v[3] = a1b1 - a0b0;
+
+    const T Eh = T(0.5) * rs;
+    T cs;  // colour sum of |chain|^2
+    if constexpr (NG == 0) {
+      const Cx<T> A = sbar_top(Lc, Sp<T>{{T(0), T(0)}, {T(1), T(0)}});
+      cs = T(3) * norm2(A);
+    } else {
+      T q[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) q[c] = p[NOUT - 2][c] + p[NOUT - 1][c];
+      const Sp<T> uL = sbar_u(Lc);  // W first from the u end
+      const T Pq[4] = {Eh - q[0], -q[1], -q[2], Eh - q[3]};  // p_u - q
+      if constexpr (NG == 1) {
+        const CV<T> e = eps_out(p[0], pt[0], (hel & 1) ? T(1) : T(-1));
+        const T Pk[4] = {Eh - p[0][0], -p[0][1], -p[0][2], Eh - p[0][3]};
+        const Cx<T> A = sbar_top(Lc, prop(Pk, sbar_u(e))) + sbar_top(e, prop(Pq, uL));
+        cs = T(4) * norm2(A);
+      } else {
+        const T(&k1)[4] = p[0];
+        const T(&k2)[4] = p[1];
+        const CV<T> e1 = eps_out(k1, pt[0], (hel & 1) ? T(1) : T(-1));
+        const CV<T> e2 = eps_out(k2, pt[1], (hel & 2) ? T(1) : T(-1));
+        // off-shell gluon of the three-gluon vertex, V / K^2 with
+        // V = (e1.e2)(k2 - k1) - 2 (k2.e1) e2 + 2 (k1.e2) e1 (e^0 = 0)
+        const T K[4] = {k1[0] + k2[0], k1[1] + k2[1], k1[2] + k2[2], k1[3] + k2[3]};
+        const T iK2 = vrcp(fma(K[0], K[0], -fma(K[1], K[1], fma(K[2], K[2], K[3] * K[3]))));
+        Cx<T> e12 = {T(0), T(0)}, k2e1 = {T(0), T(0)}, k1e2 = {T(0), T(0)};
+#pragma unroll
+        for (int c = 1; c < 4; ++c) {
+          e12 = e12 - e1.v[c] * e2.v[c];
+          k2e1 = k2e1 - k2[c] * e1.v[c];
+          k1e2 = k1e2 - k1[c] * e2.v[c];
+        }
+        CV<T> J;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          J.v[c] = iK2 * ((k2[c] - k1[c]) * e12 - T(2) * (k2e1 * e2.v[c]) + T(2) * (k1e2 * e1.v[c]));
+        const T Pk1[4] = {Eh - k1[0], -k1[1], -k1[2], Eh - k1[3]};
+        const T Pk2[4] = {Eh - k2[0], -k2[1], -k2[2], Eh - k2[3]};
+        const T PK[4] = {Eh - K[0], -K[1], -K[2], Eh - K[3]};
+        const T Pk1q[4] = {Pk1[0] - q[0], Pk1[1] - q[1], Pk1[2] - q[2], Pk1[3] - q[3]};
+        const T Pk2q[4] = {Pk2[0] - q[0], Pk2[1] - q[1], Pk2[2] - q[2], Pk2[3] - q[3]};
+        const Sp<T> ya = prop(Pk2, sbar_u(e2));  // gluon 2 first
+        const Sp<T> yw = prop(Pk1, sbar_u(e1));  // gluon 1 first
+        const Sp<T> yc = prop(Pq, uL);           // W first
+        // colour T^a1 T^a2 (gluon 1 nearer the dbar end) and T^a2 T^a1
+        const Cx<T> Tt = sbar_top(Lc, prop(PK, sbar_u(J))) + sbar_top(J, yc);
+        const Cx<T> A12 = sbar_top(Lc, prop(PK, sbar(e1, ya))) + sbar_top(e1, prop(Pk2q, sbar(Lc, ya))) +
+                          sbar_top(e1, prop(Pk2q, sbar(e2, yc))) + Tt;
+        const Cx<T> A21 = sbar_top(Lc, prop(PK, sbar(e2, yw))) + sbar_top(e2, prop(Pk1q, sbar(Lc, yw))) +
+                          sbar_top(e2, prop(Pk1q, sbar(e1, yc))) - Tt;
+        cs = T(16.0 / 3.0) * (norm2(A12) + norm2(A21)) - T(4.0 / 3.0) * fma(A12.r, A21.r, A12.i * A21.i);
+      }
+    }
+    // ---- W propagator in m_munu^2 = M_{n-1}^2 (mu nu are the last pair)
+    const T m2 = Mi[NOUT - 1] * Mi[NOUT - 1];
+    const T dm = m2 - Mv2;
+    const T invD = vrcp(fma(dm, dm, M2G2));
+    T spow = T(1);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) spow *= shat;  // s^(n-3) from V_n / (2 s), s from |A|^2
+    const T f = ((pre * spow) * fluxjac) * (cs * invD);
+    if (GRAD) {
+      g[0] = f * fma(T(4) * M, dm, -twoMG2) * invD;
+      g[1] = f * m2M2G * invD;
+      g[2] = f * two_ng_over_g;
+    }
+    return f;
+  }
+};
+
+template <typename T, int D>
+using WHel = WHelF<T, (D - 5) / 3>;
+
+}  // namespace vmc

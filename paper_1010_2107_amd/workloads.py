@@ -15,7 +15,7 @@ from dataclasses import dataclass, field, replace
 import numpy as np
 
 # integrand ids (same numbering as include/vmc.h)
-CONST, LINEAR, GAUSS, DGAUSS, GAUSS_AXES, WJETS, PSVOL = range(7)
+CONST, LINEAR, GAUSS, DGAUSS, GAUSS_AXES, WJETS, PSVOL, WHEL = range(8)
 
 SQRT_S = 14000.0          # GeV, LHC (paper Sec. 6)
 PT_MIN, ETA_MAX, DR_MIN = 20.0, 2.5, 0.4
@@ -23,6 +23,10 @@ ALPHA_S = 0.118           # paper Sec. 5
 G_STRONG = math.sqrt(4.0 * math.pi * ALPHA_S)
 M_W, GAMMA_W = 80.4, 2.1
 WJETS_THETA = (M_W, GAMMA_W, G_STRONG, SQRT_S, PT_MIN, ETA_MAX, DR_MIN)
+# the paper's process with helicity amplitudes (Sec. 5): muon |eta| < 2.5,
+# gluon |eta| < 5, Durham pT_ij > 20 GeV between gluons
+ETA_GLUON, PTIJ_MIN = 5.0, 20.0
+WHEL_THETA = (M_W, GAMMA_W, G_STRONG, SQRT_S, PT_MIN, ETA_MAX, ETA_GLUON, PTIJ_MIN)
 
 
 @dataclass(frozen=True)
@@ -50,14 +54,17 @@ C2 = Workload("dgauss_d8_bases", DGAUSS, 8, 128, 5_000_000, 10, (1 / 3, 2 / 3, 0
 C2_PLAIN = replace(C2, name="dgauss_d8_vegas", ng=1, itmx=20, itmx2=0)
 C3 = Workload("wjets2_d10_vegas", WJETS, 10, 64, 10_000_000, 15, WJETS_THETA)
 C4 = Workload("wjets4_d16_vegas", WJETS, 16, 64, 50_000_000, 20, WJETS_THETA)
+# u dbar -> W+(-> mu+ nu) + 2 gluons from helicity amplitudes, d = 11
+C6 = Workload("whel2_d11_vegas", WHEL, 11, 64, 10_000_000, 15, WHEL_THETA)
 
-CONFIGS = {w.name: w for w in (C1, C2, C2_PLAIN, C3, C4)}
+CONFIGS = {w.name: w for w in (C1, C2, C2_PLAIN, C3, C4, C6)}
 DEFAULT_BENCH = C4
 
 
 def ngrad(w) -> int:
     """Number of differentiable parameters of a workload's integrand."""
-    return {CONST: 1, LINEAR: 0, GAUSS: 2, DGAUSS: 3, GAUSS_AXES: w.dim + 1, WJETS: 3, PSVOL: 0}[w.integrand]
+    return {CONST: 1, LINEAR: 0, GAUSS: 2, DGAUSS: 3, GAUSS_AXES: w.dim + 1, WJETS: 3, PSVOL: 0,
+            WHEL: 3}[w.integrand]
 
 
 @dataclass

@@ -1,0 +1,150 @@
+"""GPU parity of the helicity-amplitude integrand u dbar -> W+(-> mu+ nu)
++ n gluons (paper Sec. 5, eq. 1; n = 0, 1, 2, d = 3n + 5) against the FP64
+oracle, through the C ABI.
+
+Tolerances:
+  * FP64 instantiation, per sample: 1e-10 relative (as for the W + partons
+    toy: the oracle's m_munu^2 from boosted momenta loses (E/m)^2 ulps, the
+    W propagator's slope carries that into f); cut decisions agree except
+    within 1e-9 of a threshold; the helicity choice floor(x 2^n) agrees
+    except where x 2^n is within 1e-12 of an integer.
+  * FP32 integrand: median per-sample error <= 1e-5, 99th percentile
+    <= 2e-4, contribution-weighted <= 2e-5; iteration sums 1e-5 (S1) and
+    2e-5 (S2, plane 1); cut decisions and helicity choices may differ only
+    within 1e-4 of a threshold.
+  * The whel2 configuration (d = 11, 1e7 x 15) against an independent-seed
+    oracle reference: |I - I_ref| / sigma < 3.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1010_2107_amd import workloads as W
+from paper_1010_2107_amd.driver import integrate
+from paper_1010_2107_amd.grid import Grid
+from tests.gpu_util import announce, normwise, rel, require_gpu
+from tests.phys_util import whel_cut_margin
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+TH = W.WHEL_THETA
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _grid(d, N, seed):
+    rng = np.random.default_rng(seed)
+    w = rng.gamma(2.0, size=(d, N)) + 0.05
+    e = np.concatenate([np.zeros((d, 1)), np.cumsum(w, axis=1)], axis=1)
+    e /= e[:, -1:]
+    e[:, -1] = 1.0
+    return e
+
+
+def _hel_edge(x, n, tol):
+    """True where the helicity variable sits within tol of a configuration boundary."""
+    v = x[:, -1] * (1 << n)
+    return np.abs(v - np.round(v)) < tol * (1 << n)
+
+
+@pytest.mark.parametrize("d", [5, 8, 11])
+def test_fp64_per_sample(d):
+    announce(f"whel fp64 per-sample d={d}")
+    N, ncall, count = 64, 10_000_000, 20_000
+    n = (d - 5) // 3
+    e = _grid(d, N, d)
+    g = Grid(d, N)
+    g.set_edges(e)
+    s0 = 77_777
+    got = g.dump(W.WHEL, TH, ncall, 1234, 2, s0, count, fp64=True)
+    ref = O.eval_samples(W.WHEL, e, TH, ncall, 1234, 2, s0, count)
+    assert np.array_equal(got["words"], ref["words"])
+    ok = ~_hel_edge(ref["x"], n, 1e-12)
+    both = (got["f"] != 0) & (ref["f"] != 0) & ok
+    assert both.sum() > count // 20
+    r = np.abs(got["f"][both] - ref["f"][both]) / np.abs(ref["f"][both])
+    assert r.max() <= 1e-10, r.max()
+    for i in np.nonzero(((got["f"] != 0) != (ref["f"] != 0)) & ok)[0]:
+        assert whel_cut_margin(ref["x"][i], TH) < 1e-9, i
+
+
+@pytest.mark.parametrize("d", [8, 11])
+def test_fp32_per_sample(d):
+    announce(f"whel fp32 per-sample d={d}")
+    N, ncall, count = 64, 10_000_000, 50_000
+    n = (d - 5) // 3
+    e = _grid(d, N, 100 + d)
+    g = Grid(d, N)
+    g.set_edges(e)
+    got = g.dump(W.WHEL, TH, ncall, 1234, 5, 2_000_000, count)
+    ref = O.eval_samples(W.WHEL, e, TH, ncall, 1234, 5, 2_000_000, count)
+    ok = ~_hel_edge(ref["x"], n, 1e-6)
+    both = (got["f"] != 0) & (ref["f"] != 0) & ok
+    r = np.abs(got["f"][both] - ref["f"][both]) / np.abs(ref["f"][both])
+    print(f"d={d} pass={both.mean():.3f} rel err median {np.median(r):.2e} p99 {np.quantile(r, .99):.2e} "
+          f"max {r.max():.2e}")
+    assert np.median(r) <= 1e-5
+    assert np.quantile(r, 0.99) <= 2e-4
+    for i in np.nonzero(((got["f"] != 0) != (ref["f"] != 0)) & ok)[0]:
+        assert whel_cut_margin(ref["x"][i], TH) < 1e-4, i
+    wsum = np.sum(np.abs(got["w"][both] - ref["w"][both])) / np.sum(np.abs(ref["w"][ok]))
+    assert wsum <= 2e-5, wsum
+
+
+@pytest.mark.parametrize("d,ncall", [(8, 1_000_003), (11, 1_000_003)])
+def test_iteration_sums_same_grid(d, ncall):
+    announce(f"whel sums d={d}")
+    N = 64
+    e = O.integrate(W.WHEL, d, N, TH, 100_000, 3, 77).edges
+    g = Grid(d, N)
+    g.set_edges(e)
+    g.iterate(W.WHEL, TH, ncall, 1234, 9)
+    r = g.result()
+    ref = O.iterate(W.WHEL, e, TH, ncall, 1234, 9)
+    print(f"d={d} S1 rel {rel(r['S1'], ref['S1']):.2e} S2 rel {rel(r['S2'], ref['S2']):.2e}")
+    assert rel(r["S1"], ref["S1"]) <= 1e-5
+    assert rel(r["S2"], ref["S2"]) <= 2e-5
+    b = g.bins.cpu().numpy()
+    assert normwise(b[0], ref["bins"][0]) <= 1e-5
+    assert normwise(b[1], ref["bins"][1]) <= 2e-5
+    # FP64 instantiation, plain and stratified, forward and adjoint sums
+    for ng, nc in ((1, 200_003), (2, 2 ** d * 40 + 3)):
+        g = Grid(d, N)
+        g.stratify(ng)
+        g.set_edges(e)
+        g.fused(W.WHEL, TH, nc, 1234, 4, fp64=True)
+        r = g.result()
+        ref = O.iterate(W.WHEL, e, TH, nc, 1234, 4, ng=ng, want_grad=True)
+        assert rel(r["S1"], ref["S1"]) <= 1e-10 and rel(r["S2"], ref["S2"]) <= 1e-10
+        assert normwise(g.bins.cpu().numpy(), ref["bins"]) <= 1e-10
+        gr = g.grad_result(3)
+        assert np.all(np.abs(gr["grad"] - ref["grad"]) <= 1e-10 * np.abs(ref["grad"]) + 1e-300)
+
+
+def test_coupling_identity():
+    """g_s dI/dg_s = 2 n I on the same samples (n = 2)."""
+    announce("whel coupling identity")
+    d, N, ncall = 11, 64, 500_000
+    e = O.integrate(W.WHEL, d, N, TH, 50_000, 2, 5).edges
+    g = Grid(d, N)
+    g.set_edges(e)
+    g.fused(W.WHEL, TH, ncall, 99, 1)
+    r = g.result()
+    gr = g.grad_result(3)
+    assert abs(TH[2] * gr["grad"][2] / (4 * r["I"]) - 1) < 1e-5
+
+
+def test_configuration_against_oracle_reference():
+    w = W.C6
+    announce(f"end-to-end {w.name}")
+    ref = json.load(open(os.path.join(HERE, "golden", "whel_reference.json")))[str(w.dim)]
+    r = integrate(w.integrand, w.dim, w.nbins, w.theta, w.ncall, w.itmx, w.seed, alpha=w.alpha)
+    z = abs(r.Ibar - ref["Ibar"]) / np.hypot(r.sigbar, ref["sigbar"])
+    print(f"{w.name}: GPU {r.Ibar:.6g} +- {r.sigbar:.3g}, oracle {ref['Ibar']:.6g} +- {ref['sigbar']:.3g}, z={z:.2f}")
+    assert z < 3
