@@ -11,6 +11,8 @@
 // so any pass can regenerate any sample.
 #pragma once
 
+#include <type_traits>
+
 #include "vmc_device.hpp"
 
 namespace vmc {
@@ -124,6 +126,31 @@ __device__ inline void finalize_one(double* scal, int strat, double n, double kd
     g[3] = G;
     g[4] = strat ? g[2] / denom : (g[1] / n - G * G) / (n - 1.0);
   }
+}
+
+// Integrands that split their evaluation at the cuts (stage1: map, phase
+// space, cuts; stage2: the matrix element) set kStaged; the plain kernel
+// then queues the samples that pass in LDS, per wave, and runs stage 2 on
+// full waves of queued samples.
+template <class F, class = void>
+struct StagedTraits {
+  static constexpr bool value = false;
+  static constexpr int words = 0;
+};
+template <class F>
+struct StagedTraits<F, std::void_t<decltype(F::kStaged)>> {
+  static constexpr bool value = F::kStaged;
+  static constexpr int words = F::kStateWords;
+};
+constexpr int kQueueCap = 2 * kWave;  // entries per wave: up to 63 waiting + 64 new
+// queue words per entry: the state, the Jacobian and the bin indices (4 per word)
+template <class F>
+constexpr int queue_words() {
+  return StagedTraits<F>::words + 1 + (F::D + 3) / 4;
+}
+template <class F>
+constexpr int queue_bytes() {
+  return StagedTraits<F>::value ? (kBlock / kWave) * kQueueCap * queue_words<F>() * 4 : 0;
 }
 
 // LDS layout: grid table first (16-byte entries for FP64), then histogram.
@@ -282,18 +309,84 @@ __global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
   uint32_t cnt[2] = {0u, 0u};  // non-finite and zero weights
 
   const uint32_t dummy_cc[D] = {};
-  for (uint64_t t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
-    const uint64_t b0 = t * A.block_items;
-    const uint64_t b1 = min(b0 + A.block_items, A.ncall);
-    for (uint64_t s = b0 + threadIdx.x; s < b1; s += kBlock) {
-      uint32_t w[D];
-      sample_words<D>(static_cast<uint32_t>(s), A.it, A.kid, A.key, w);
+  if constexpr (StagedTraits<F>::value) {
+    // per-wave LDS queue (structure of arrays) of samples that passed stage 1
+    constexpr int NQ = queue_words<F>();
+    constexpr int NS = StagedTraits<F>::words;
+    const int lane = threadIdx.x & (kWave - 1);
+    // after the histogram (forward passes) or right after the table
+    float* q = reinterpret_cast<float*>(hist + ((KIND & KIND_FWD) ? 2 * D * A.nbins : 0)) +
+               (threadIdx.x / kWave) * NQ * kQueueCap;
+    uint32_t* qj = reinterpret_cast<uint32_t*>(q + (NS + 1) * kQueueCap);
+    int qn = 0;  // entries waiting (wave-uniform)
+    auto run = [&](int e) {
+      const typename F::State st = F::load_state(q, kQueueCap, e);
+      const T jac = static_cast<T>(q[NS * kQueueCap + e]);
       int j[D];
-      T x[D], jac;
-      make_point<T, D, false>(A, tab, w, dummy_cc, j, x, jac);
+#pragma unroll
+      for (int a = 0; a < D; a += 4) {
+        const uint32_t pk = qj[(a / 4) * kQueueCap + e];
+#pragma unroll
+        for (int b = 0; b < 4 && a + b < D; ++b) j[a + b] = static_cast<int>((pk >> (8 * b)) & 0xFFu);
+      }
       T g[F::NGRAD + 1];
-      const T fv = fn.template eval<(KIND & KIND_ADJ) != 0>(x, g);
+      const T fv = fn.template stage2<(KIND & KIND_ADJ) != 0>(st, g);
       accumulate<F, KIND>(A, hist, j, fv, jac, g, acc, cnt);
+    };
+    for (uint64_t t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
+      const uint64_t b0 = t * A.block_items;
+      const uint64_t b1 = min(b0 + A.block_items, A.ncall);
+      for (uint64_t base = b0; base < b1; base += kBlock) {
+        const uint64_t s = base + threadIdx.x;
+        bool pass = false;
+        typename F::State st;
+        int j[D];
+        T jac = T(0);
+        if (s < b1) {
+          uint32_t w[D];
+          sample_words<D>(static_cast<uint32_t>(s), A.it, A.kid, A.key, w);
+          T x[D];
+          make_point<T, D, false>(A, tab, w, dummy_cc, j, x, jac);
+          pass = fn.stage1(x, st);
+          cnt[1] += pass ? 0u : 1u;  // f = 0 outside the cuts: nothing else to add
+        }
+        const uint64_t m = __ballot(pass);
+        if (pass) {
+          const int e = qn + static_cast<int>(__popcll(m & __lanemask_lt()));
+          F::store_state(st, q, kQueueCap, e);
+          q[NS * kQueueCap + e] = static_cast<float>(jac);
+#pragma unroll
+          for (int a = 0; a < D; a += 4) {
+            uint32_t pk = 0;
+#pragma unroll
+            for (int b = 0; b < 4 && a + b < D; ++b) pk |= static_cast<uint32_t>(j[a + b]) << (8 * b);
+            qj[(a / 4) * kQueueCap + e] = pk;
+          }
+        }
+        qn += static_cast<int>(__popcll(m));
+        __builtin_amdgcn_wave_barrier();
+        if (qn >= kWave) {  // a full wave of queued samples: the newest 64
+          qn -= kWave;
+          run(qn + lane);
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+    }
+    if (lane < qn) run(lane);
+  } else {
+    for (uint64_t t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
+      const uint64_t b0 = t * A.block_items;
+      const uint64_t b1 = min(b0 + A.block_items, A.ncall);
+      for (uint64_t s = b0 + threadIdx.x; s < b1; s += kBlock) {
+        uint32_t w[D];
+        sample_words<D>(static_cast<uint32_t>(s), A.it, A.kid, A.key, w);
+        int j[D];
+        T x[D], jac;
+        make_point<T, D, false>(A, tab, w, dummy_cc, j, x, jac);
+        T g[F::NGRAD + 1];
+        const T fv = fn.template eval<(KIND & KIND_ADJ) != 0>(x, g);
+        accumulate<F, KIND>(A, hist, j, fv, jac, g, acc, cnt);
+      }
     }
   }
   acc[2] = static_cast<double>(cnt[0]);

@@ -281,8 +281,36 @@ struct WJetsF {
     }
   }
 
-  template <bool GRAD>
-  __device__ __forceinline__ T eval(const T (&x)[D], T (&g)[NGRAD + 1]) const {
+  // The evaluation in two stages so that a kernel can queue the samples
+  // that pass the cuts and run the colour sum on full waves: stage 1 maps
+  // x to momenta, applies the cuts and keeps the scaled invariants y_kl of
+  // the coloured set (upper triangle), m_enu^2 and the prefactor; stage 2
+  // forms |M|^2 and f from them.
+  static constexpr int NY = MC * (MC - 1) / 2;
+  struct State {
+    T y[NY];
+    T m2, pref;  // pref = pre s^(n-3) flux Jacobian s^4 / c^m
+  };
+  static constexpr int kStateWords = NY + 2;
+  static constexpr bool kStaged = FULL && sizeof(T) == 4;  // the queue holds FP32
+
+  __device__ __forceinline__ static void store_state(const State& st, float* q, int stride, int e) {
+#pragma unroll
+    for (int i = 0; i < NY; ++i) q[i * stride + e] = static_cast<float>(st.y[i]);
+    q[NY * stride + e] = static_cast<float>(st.m2);
+    q[(NY + 1) * stride + e] = static_cast<float>(st.pref);
+  }
+  __device__ __forceinline__ static State load_state(const float* q, int stride, int e) {
+    State st;
+#pragma unroll
+    for (int i = 0; i < NY; ++i) st.y[i] = static_cast<T>(q[i * stride + e]);
+    st.m2 = static_cast<T>(q[NY * stride + e]);
+    st.pref = static_cast<T>(q[(NY + 1) * stride + e]);
+    return st;
+  }
+
+  // PDF map, phase space and cuts; false when the sample fails the cuts
+  __device__ __forceinline__ bool stage1(const T (&x)[D], State& st) const {
     // parton fractions and flux x Jacobian = L^2 x0 tau^-1/2 ((1-xa)(1-xb))^3
     const T la = L * (T(1) - x[0]);
     const T lb = L * x[0] * (T(1) - x[1]);
@@ -295,101 +323,128 @@ struct WJetsF {
     T spow = T(1);
 #pragma unroll
     for (int i = 0; i < NOUT - 3; ++i) spow *= shat;
-    if constexpr (!FULL) {
-      return pre * fluxjac * spow;
-    } else {
-      const T yb = T(0.5) * (la - lb);
-      // ---- RAMBO on diet: masses M_1 = sqrt(s) > M_2 > ... > M_{n-1} > M_n = 0
-      T Mi[NOUT + 1], Ui[NOUT + 1];
-      T p[NOUT][4];
-      rambo_diet<NOUT, 2>(x, rs, Mi, Ui, p);
+    const T yb = T(0.5) * (la - lb);
+    // ---- RAMBO on diet: masses M_1 = sqrt(s) > M_2 > ... > M_{n-1} > M_n = 0
+    T Mi[NOUT + 1], Ui[NOUT + 1];
+    T p[NOUT][4];
+    rambo_diet<NOUT, 2>(x, rs, Mi, Ui, p);
 
-      // ---- visible particles: partons 0..NP-1 and the electron NP
-      constexpr int NV = NP + 1;
-      T pt2[NV], pt[NV], rpt2[NV], lp[NV], lm[NV], eta[NV];
-      bool pass = true;
+    // ---- visible particles: partons 0..NP-1 and the electron NP
+    constexpr int NV = NP + 1;
+    T pt2[NV], pt[NV], rpt2[NV], lp[NV], lm[NV], eta[NV];
+    bool pass = true;
 #pragma unroll
-      for (int j = 0; j < NV; ++j) {
-        const LightCone<T> lc = light_cone(p[j]);
-        pt2[j] = lc.pt2;
-        pt[j] = lc.pt;
-        rpt2[j] = lc.rpt2;
-        lp[j] = lc.lp;
-        lm[j] = lc.lm;
-        eta[j] = lc.eta;
-        pass = pass && (pt2[j] > ptmin2) && (fabs(eta[j] + yb) < etamax);
-      }
-      // Delta R > R: either Delta eta^2 >= R^2, or cos(Delta phi) < cos(phi0)
-      // with phi0 = sqrt(R^2 - Delta eta^2) <= R; cos(phi0) from its Taylor
-      // series in z = phi0^2 (terms to z^6; remainder below 1e-16 for R <= 0.4).
-#pragma unroll
-      for (int i = 0; i < NV; ++i)
-#pragma unroll
-        for (int j = i + 1; j < NV; ++j) {
-          const T de = eta[i] - eta[j];
-          const T z = dr2 - de * de;
-          T c;
-          if constexpr (sizeof(T) == 8) {
-            c = T(1.0 / 479001600.0);
-            c = fma(c, -z, T(1.0 / 3628800.0));
-            c = fma(c, -z, T(1.0 / 40320.0));
-          } else {
-            c = T(1.0 / 40320.0);  // z^5 term < 3e-11 for z <= 0.16
-          }
-          c = fma(c, -z, T(1.0 / 720.0));
-          c = fma(c, -z, T(1.0 / 24.0));
-          c = fma(c, -z, T(1.0 / 2.0));
-          c = fma(c, -z, T(1));
-          const T dot = p[i][1] * p[j][1] + p[i][2] * p[j][2];
-          pass = pass && ((z <= T(0)) || (dot < c * pt[i] * pt[j]));
-        }
-      if (GRAD) {
-        g[0] = g[1] = g[2] = T(0);
-      }
-      if (!pass) return T(0);
-
-      // ---- invariants of the coloured set, scaled: y = c / s_kl with c a power
-      // of two near s^(4/m), so s^4 / prod s = (s^4 / c^m) prod y exactly
-      const int ce = (4 * ilogb_(shat)) / MC;
-      const T c = ldexp_(T(1), ce);
-      T y[MC][MC];
-      const T crs = c * vrcp(rs);
-      y[0][1] = y[1][0] = crs * vrcp(rs);
-#pragma unroll
-      for (int j = 0; j < NP; ++j) {
-        const T ya = crs * lp[j] * rpt2[j];   // c / s_aj, s_aj = sqrt(s) (E - pz)
-        const T yb2 = crs * lm[j] * rpt2[j];  // c / s_bj, s_bj = sqrt(s) (E + pz)
-        y[0][2 + j] = y[2 + j][0] = ya;
-        y[1][2 + j] = y[2 + j][1] = yb2;
-      }
-#pragma unroll
-      for (int i = 0; i < NP; ++i)
-#pragma unroll
-        for (int j = i + 1; j < NP; ++j) {
-          const T s = fma(lp[i], lm[j], lm[i] * lp[j]) - T(2) * (p[i][1] * p[j][1] + p[i][2] * p[j][2]);
-          y[2 + i][2 + j] = y[2 + j][2 + i] = c * vrcp(s);
-        }
-#pragma unroll
-      for (int i = 0; i < MC; ++i) y[i][i] = T(0);
-      const T ptsum = cycle_sum<MC, T>(y);
-
-      // ---- Breit-Wigner in m_enu^2 = M_{n-1}^2 (e nu are the last pair)
-      const T m2 = Mi[NOUT - 1] * Mi[NOUT - 1];
-      const T dm = m2 - Mv2;
-      const T invD = vrcp(fma(dm, dm, M2G2));
-      const T bw = MGpi * invD;
-      const T s2 = shat * shat;
-      const T s4c = ldexp_(s2 * s2, -ce * MC);  // s^4 / c^m
-      const T f = ((pre * spow) * fluxjac) * bw * (ptsum * s4c);
-      if (GRAD) {
-        g[0] = f * (invM - fma(T(-4) * M, dm, twoMG2) * invD);
-        g[1] = f * (invG - T(2) * M * MG * invD);
-        g[2] = f * two_np_over_g;
-      }
-      return f;
+    for (int j = 0; j < NV; ++j) {
+      const LightCone<T> lc = light_cone(p[j]);
+      pt2[j] = lc.pt2;
+      pt[j] = lc.pt;
+      rpt2[j] = lc.rpt2;
+      lp[j] = lc.lp;
+      lm[j] = lc.lm;
+      eta[j] = lc.eta;
+      pass = pass && (pt2[j] > ptmin2) && (fabs(eta[j] + yb) < etamax);
     }
+    // Delta R > R: either Delta eta^2 >= R^2, or cos(Delta phi) < cos(phi0)
+    // with phi0 = sqrt(R^2 - Delta eta^2) <= R; cos(phi0) from its Taylor
+    // series in z = phi0^2 (terms to z^6; remainder below 1e-16 for R <= 0.4).
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int j = i + 1; j < NV; ++j) {
+        const T de = eta[i] - eta[j];
+        const T z = dr2 - de * de;
+        T c;
+        if constexpr (sizeof(T) == 8) {
+          c = T(1.0 / 479001600.0);
+          c = fma(c, -z, T(1.0 / 3628800.0));
+          c = fma(c, -z, T(1.0 / 40320.0));
+        } else {
+          c = T(1.0 / 40320.0);  // z^5 term < 3e-11 for z <= 0.16
+        }
+        c = fma(c, -z, T(1.0 / 720.0));
+        c = fma(c, -z, T(1.0 / 24.0));
+        c = fma(c, -z, T(1.0 / 2.0));
+        c = fma(c, -z, T(1));
+        const T dot = p[i][1] * p[j][1] + p[i][2] * p[j][2];
+        pass = pass && ((z <= T(0)) || (dot < c * pt[i] * pt[j]));
+      }
+    if (!pass) return false;
+
+    // ---- invariants of the coloured set, scaled: y = c / s_kl with c a power
+    // of two near s^(4/m), so s^4 / prod s = (s^4 / c^m) prod y exactly
+    const int ce = (4 * ilogb_(shat)) / MC;
+    const T c = ldexp_(T(1), ce);
+    const T crs = c * vrcp(rs);
+    int k = 0;
+    st.y[k++] = crs * vrcp(rs);  // (0,1)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) st.y[k++] = crs * lp[j] * rpt2[j];  // (0, 2+j): c / s_aj, s_aj = sqrt(s)(E - pz)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) st.y[k++] = crs * lm[j] * rpt2[j];  // (1, 2+j): c / s_bj
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+      for (int j = i + 1; j < NP; ++j) {
+        const T sij = fma(lp[i], lm[j], lm[i] * lp[j]) - T(2) * (p[i][1] * p[j][1] + p[i][2] * p[j][2]);
+        st.y[k++] = c * vrcp(sij);  // (2+i, 2+j)
+      }
+    st.m2 = Mi[NOUT - 1] * Mi[NOUT - 1];
+    const T s2 = shat * shat;
+    st.pref = ((pre * spow) * fluxjac) * ldexp_(s2 * s2, -ce * MC);
+    return true;
   }
 
+  // |M|^2 and f of a sample that passed the cuts
+  template <bool GRAD>
+  __device__ __forceinline__ T stage2(const State& st, T (&g)[NGRAD + 1]) const {
+    T y[MC][MC];
+    int k = 0;
+    y[0][1] = y[1][0] = st.y[k++];
+#pragma unroll
+    for (int j = 0; j < NP; ++j, ++k) y[0][2 + j] = y[2 + j][0] = st.y[k];
+#pragma unroll
+    for (int j = 0; j < NP; ++j, ++k) y[1][2 + j] = y[2 + j][1] = st.y[k];
+#pragma unroll
+    for (int i = 0; i < NP; ++i)
+#pragma unroll
+      for (int j = i + 1; j < NP; ++j, ++k) y[2 + i][2 + j] = y[2 + j][2 + i] = st.y[k];
+#pragma unroll
+    for (int i = 0; i < MC; ++i) y[i][i] = T(0);
+    const T ptsum = cycle_sum<MC, T>(y);
+    // ---- Breit-Wigner in m_enu^2 = M_{n-1}^2 (e nu are the last pair)
+    const T dm = st.m2 - Mv2;
+    const T invD = vrcp(fma(dm, dm, M2G2));
+    const T f = st.pref * (MGpi * invD) * ptsum;
+    if (GRAD) {
+      g[0] = f * (invM - fma(T(-4) * M, dm, twoMG2) * invD);
+      g[1] = f * (invG - T(2) * M * MG * invD);
+      g[2] = f * two_np_over_g;
+    }
+    return f;
+  }
+
+  template <bool GRAD>
+  __device__ __forceinline__ T eval(const T (&x)[D], T (&g)[NGRAD + 1]) const {
+    if constexpr (!FULL) {
+      const T la = L * (T(1) - x[0]);
+      const T lb = L * x[0] * (T(1) - x[1]);
+      const T h = vexp(T(0.5) * (la + lb));
+      const T shat = sqrtS * h * (sqrtS * h);
+      const T om = vexpm1(la) * vexpm1(lb);
+      const T fluxjac = LL * x[0] * (om * om * om) * vrcp(h);
+      T spow = T(1);
+#pragma unroll
+      for (int i = 0; i < NOUT - 3; ++i) spow *= shat;
+      return pre * fluxjac * spow;
+    } else {
+      State st;
+      if (!stage1(x, st)) {
+        if (GRAD) g[0] = g[1] = g[2] = T(0);
+        return T(0);
+      }
+      return stage2<GRAD>(st, g);
+    }
+  }
 };
 
 template <typename T, int D>
