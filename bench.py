@@ -252,6 +252,41 @@ def spring_leg(trials=50_000_000):
     return out
 
 
+# The paper's GPU timings of its own process, u dbar -> W+ + n gluons, on a
+# GTX285 (Table 7; NCALL = 1e6 for n <= 2, ITMX = 10 or ITMX1 = ITMX2 = 5),
+# as calls per second: context only, other hardware.
+PAPER_GTX285_CALLS_PER_S = {0: {"vegas": 1 / 0.0207e-6, "bases": 1 / 0.0260e-6},
+                            1: {"vegas": 1 / 0.0318e-6, "bases": 1 / 0.0396e-6},
+                            2: {"vegas": 1 / 0.0497e-6, "bases": 1 / 0.0563e-6}}
+
+
+def paper_process_leg():
+    """The paper's process at the paper's run sizes (Table 5: NCALL 1e6,
+    ITMX 10 for VEGAS, ITMX1 = ITMX2 = 5 for BASES), helicity amplitudes in
+    FP32, whole iteration loop timed (sample pass, publish, refine)."""
+    import torch
+
+    from paper_1010_2107_amd import workloads as W
+    from paper_1010_2107_amd.grid import Grid
+
+    out = {}
+    for n in (0, 1, 2):
+        d = 3 * n + 5
+        ng = {5: 4, 8: 2, 11: 2}[d]  # ng^d <= NCALL / 2
+        for mode in ("vegas", "bases"):
+            w = W.Workload(f"whel{n}_d{d}_{mode}", W.WHEL, d, 64, 1_000_000, 10 if mode == "vegas" else 5,
+                           W.WHEL_THETA, ng=1 if mode == "vegas" else ng, itmx2=0 if mode == "vegas" else 5)
+            g = Grid(d, 64)
+            steps = w.itmx + w.itmx2
+            run_loop(g, w, steps)  # warm-up
+            ms, kms, nl = run_loop(g, w, steps)
+            r = g.result()
+            rate = r["n_eff"] * steps / (ms / 1e3)
+            out[w.name] = {"calls_per_s": rate, "kernel_ms_per_launch": kms / max(nl, 1), "Ibar": r["Ibar"],
+                           "sigbar": r["sigbar"], "paper_gtx285_calls_per_s": PAPER_GTX285_CALLS_PER_S[n][mode]}
+    return out
+
+
 def host_accumulation_leg(iters=3):
     """The paper's split of the work (Sec. 3.2): the GPU generates the
     points and evaluates the integrand, the weights and bin indices are
@@ -420,6 +455,8 @@ def main(argv=None):
         line["secondary"] = sec
         print("[bench] batched leg", file=sys.stderr, flush=True)
         line["batched"] = batched_leg()
+        print("[bench] paper's process at the paper's sizes", file=sys.stderr, flush=True)
+        line["paper_process"] = paper_process_leg()
         print("[bench] spring leg", file=sys.stderr, flush=True)
         line["spring"] = spring_leg()
         print("[bench] host-accumulation ablation", file=sys.stderr, flush=True)

@@ -156,8 +156,40 @@ struct WHelF {
     return e;
   }
 
-  template <bool GRAD>
-  __device__ __forceinline__ T eval(const T (&x)[D], T (&g)[NGRAD + 1]) const {
+  // The evaluation in two stages so that a kernel can queue the samples
+  // that pass the cuts and evaluate the amplitudes on full waves: stage 1
+  // maps x to momenta and applies the cuts; stage 2 forms |M|^2 and f.
+  struct State {
+    T p[NOUT][4];  // g_1..g_NG, mu+, nu in the partonic frame
+    T Eh, m2, pref, hel;  // sqrt(s)/2, m_munu^2, prefactor, helicity configuration
+  };
+  static constexpr int kStateWords = 4 * NOUT + 4;
+  static constexpr bool kStaged = sizeof(T) == 4;  // the queue holds FP32
+
+  __device__ __forceinline__ static void store_state(const State& st, float* q, int stride, int e) {
+#pragma unroll
+    for (int i = 0; i < NOUT; ++i)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) q[(4 * i + c) * stride + e] = static_cast<float>(st.p[i][c]);
+    q[(4 * NOUT + 0) * stride + e] = static_cast<float>(st.Eh);
+    q[(4 * NOUT + 1) * stride + e] = static_cast<float>(st.m2);
+    q[(4 * NOUT + 2) * stride + e] = static_cast<float>(st.pref);
+    q[(4 * NOUT + 3) * stride + e] = static_cast<float>(st.hel);
+  }
+  __device__ __forceinline__ static State load_state(const float* q, int stride, int e) {
+    State st;
+#pragma unroll
+    for (int i = 0; i < NOUT; ++i)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) st.p[i][c] = static_cast<T>(q[(4 * i + c) * stride + e]);
+    st.Eh = static_cast<T>(q[(4 * NOUT + 0) * stride + e]);
+    st.m2 = static_cast<T>(q[(4 * NOUT + 1) * stride + e]);
+    st.pref = static_cast<T>(q[(4 * NOUT + 2) * stride + e]);
+    st.hel = static_cast<T>(q[(4 * NOUT + 3) * stride + e]);
+    return st;
+  }
+
+  __device__ __forceinline__ bool stage1(const T (&x)[D], State& st) const {
     const T la = L * (T(1) - x[0]);
     const T lb = L * x[0] * (T(1) - x[1]);
     const T h = vexp(T(0.5) * (la + lb));  // sqrt(tau)
@@ -167,9 +199,8 @@ struct WHelF {
     const T fluxjac = LL * x[0] * (om * om * om) * vrcp(h);
     const T yb = T(0.5) * (la - lb);
     T Mi[NOUT + 1], Ui[NOUT + 1];
-    T p[NOUT][4];
-    rambo_diet<NOUT, 2>(x, rs, Mi, Ui, p);
-    if (GRAD) g[0] = g[1] = g[2] = T(0);
+    rambo_diet<NOUT, 2>(x, rs, Mi, Ui, st.p);
+    const auto& p = st.p;
 
     // ---- cuts: gluons 0..NG-1, the muon NG
     bool pass = true;
@@ -198,11 +229,24 @@ struct WHelF {
       }
       pass = pass && ((z <= T(0)) || (z < T(9.869604401089358) && dot < cz * pt[0] * pt[1]));
     }
-    if (!pass) return T(0);
+    if (!pass) return false;
+    T spow = T(1);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) spow *= shat;  // s^(n-3) from V_n / (2 s), s from |A|^2
+    st.Eh = T(0.5) * rs;
+    st.m2 = Mi[NOUT - 1] * Mi[NOUT - 1];
+    st.pref = (pre * spow) * fluxjac;
+    // the gluon helicity configuration, floor(x 2^NG)
+    const int hel = static_cast<int>(x[D - 1] * T(1 << NG));
+    st.hel = static_cast<T>(hel < (1 << NG) - 1 ? hel : (1 << NG) - 1);
+    return true;
+  }
 
-    // ---- helicity configuration of the gluons
-    int hel = static_cast<int>(x[D - 1] * T(1 << NG));
-    hel = hel < (1 << NG) - 1 ? hel : (1 << NG) - 1;
+  template <bool GRAD>
+  __device__ __forceinline__ T stage2(const State& st, T (&g)[NGRAD + 1]) const {
+    const auto& p = st.p;
+    const int hel = static_cast<int>(st.hel);
+    const T Eh = st.Eh;
 
     // ---- lepton current L = u_L(nu)^dagger sigmabar v_L(mu), sigmabar = (1, -sigma)
     const Sp<T> a = weyl(p[NOUT - 1]);
@@ -215,7 +259,6 @@ struct WHelF {
     Lc.v[2] = {-(a0b1.i - a1b0.i), a0b1.r - a1b0.r};  // i (a0* b1 - a1* b0)
     Lc.v[3] = a1b1 - a0b0;
 
-    const T Eh = T(0.5) * rs;
     T cs;  // colour sum of |chain|^2
     if constexpr (NG == 0) {
       const Cx<T> A = sbar_top(Lc, Sp<T>{{T(0), T(0)}, {T(1), T(0)}});
@@ -227,15 +270,17 @@ struct WHelF {
       const Sp<T> uL = sbar_u(Lc);  // W first from the u end
       const T Pq[4] = {Eh - q[0], -q[1], -q[2], Eh - q[3]};  // p_u - q
       if constexpr (NG == 1) {
-        const CV<T> e = eps_out(p[0], pt[0], (hel & 1) ? T(1) : T(-1));
+        const T ptg = vsqrt(p[0][1] * p[0][1] + p[0][2] * p[0][2]);
+        const CV<T> e = eps_out(p[0], ptg, (hel & 1) ? T(1) : T(-1));
         const T Pk[4] = {Eh - p[0][0], -p[0][1], -p[0][2], Eh - p[0][3]};
         const Cx<T> A = sbar_top(Lc, prop(Pk, sbar_u(e))) + sbar_top(e, prop(Pq, uL));
         cs = T(4) * norm2(A);
       } else {
         const T(&k1)[4] = p[0];
         const T(&k2)[4] = p[1];
-        const CV<T> e1 = eps_out(k1, pt[0], (hel & 1) ? T(1) : T(-1));
-        const CV<T> e2 = eps_out(k2, pt[1], (hel & 2) ? T(1) : T(-1));
+        const T pt1 = vsqrt(k1[1] * k1[1] + k1[2] * k1[2]), pt2v = vsqrt(k2[1] * k2[1] + k2[2] * k2[2]);
+        const CV<T> e1 = eps_out(k1, pt1, (hel & 1) ? T(1) : T(-1));
+        const CV<T> e2 = eps_out(k2, pt2v, (hel & 2) ? T(1) : T(-1));
         // off-shell gluon of the three-gluon vertex, V / K^2 with
         // V = (e1.e2)(k2 - k1) - 2 (k2.e1) e2 + 2 (k1.e2) e1 (e^0 = 0)
         const T K[4] = {k1[0] + k2[0], k1[1] + k2[1], k1[2] + k2[2], k1[3] + k2[3]};
@@ -269,19 +314,25 @@ struct WHelF {
       }
     }
     // ---- W propagator in m_munu^2 = M_{n-1}^2 (mu nu are the last pair)
-    const T m2 = Mi[NOUT - 1] * Mi[NOUT - 1];
-    const T dm = m2 - Mv2;
+    const T dm = st.m2 - Mv2;
     const T invD = vrcp(fma(dm, dm, M2G2));
-    T spow = T(1);
-#pragma unroll
-    for (int i = 0; i < NG; ++i) spow *= shat;  // s^(n-3) from V_n / (2 s), s from |A|^2
-    const T f = ((pre * spow) * fluxjac) * (cs * invD);
+    const T f = st.pref * (cs * invD);
     if (GRAD) {
       g[0] = f * fma(T(4) * M, dm, -twoMG2) * invD;
       g[1] = f * m2M2G * invD;
       g[2] = f * two_ng_over_g;
     }
     return f;
+  }
+
+  template <bool GRAD>
+  __device__ __forceinline__ T eval(const T (&x)[D], T (&g)[NGRAD + 1]) const {
+    State st;
+    if (!stage1(x, st)) {
+      if (GRAD) g[0] = g[1] = g[2] = T(0);
+      return T(0);
+    }
+    return stage2<GRAD>(st, g);
   }
 };
 
