@@ -272,7 +272,7 @@ def paper_process_leg():
     out = {}
     for n in (0, 1, 2):
         d = 3 * n + 5
-        ng = {5: 4, 8: 2, 11: 2}[d]  # ng^d <= NCALL / 2
+        ng = W.default_ng(1_000_000, d, 64)  # ng^d <= NCALL / 2
         for mode in ("vegas", "bases"):
             w = W.Workload(f"whel{n}_d{d}_{mode}", W.WHEL, d, 64, 1_000_000, 10 if mode == "vegas" else 5,
                            W.WHEL_THETA, ng=1 if mode == "vegas" else ng, itmx2=0 if mode == "vegas" else 5)

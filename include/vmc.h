@@ -149,7 +149,7 @@ int bases_stratify(vmc_grid_t g, int ng);
  * (device doubles, ntheta of them), accumulate sum w, sum w^2 and the
  * per-axis per-bin sums (bins buffer), then write I_k and its variance and
  * fold them into the running combination (weights 1/var).  Stream-ordered:
- * the sample kernel (resident blocks pulling tiles of samples) and a small
+ * the sample kernel (one tile of samples per block) and a small
  * publish kernel that adds up the blocks' partial sums and writes the bin
  * sums, the scalar block and the combination.  Calls on one handle must be
  * ordered on one stream: they share the bound buffers.
@@ -212,12 +212,14 @@ int vmc_dump_samples(vmc_grid_t g, int integrand, const double *theta, int nthet
                      uint64_t seed, uint32_t it, uint32_t flags, int64_t s0, int64_t count,
                      uint32_t *words, void *w, void *f, void *jac, void *stream);
 
-/* Launch shape of the sample kernels, whose resident blocks pull tiles of
- * work from a counter.  block_samples: samples (plain) or cube units
- * (stratified) per tile, a multiple of 256 in
- * [256, 2^24], or 0 for the built-in choice; chunks_per_cube: lanes that
- * share one cube in stratified mode, a power of two in [1, 64], or 0 for
- * the built-in choice.  Errors: VMC_E_SCHEDULE. */
+/* Launch shape of the sample kernels: one tile per thread block.
+ * block_samples: samples (plain) or cube units (stratified) per tile, a
+ * multiple of 256 in [256, 2^24], or 0 for the built-in choice (plain: at
+ * least 1024 tiles of at most 8192 samples; stratified: about 512 tiles);
+ * chunks_per_cube: lanes that share one cube in stratified mode, a power of
+ * two in [1, 64], or 0 for the built-in choice (the smallest power of two
+ * with ng^dim x lanes >= 2^18, at most 64 and at most k).  Errors:
+ * VMC_E_SCHEDULE. */
 int vmc_set_schedule(vmc_grid_t g, int block_samples, int chunks_per_cube);
 
 /* Kernel timing with HIP events recorded on the launch stream around every

@@ -244,12 +244,13 @@ int plan_launch(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
     A.k = static_cast<uint32_t>(k);
     A.ncall = k * M;
     P.n_eff = static_cast<double>(k * M);
-    // built-in: about 32 samples per lane, and about 512 blocks
+    // built-in lanes per cube: enough cube units (M G) to give every SIMD
+    // of the chip a few waves (2^18 lanes), at most one wave per cube and
+    // at most k lanes per cube
     uint32_t G = static_cast<uint32_t>(g->chunks);
     if (!G) {
-      uint64_t want = k / 32;
       G = 1;
-      while (G < 64 && 2 * G <= want) G <<= 1;
+      while (G < 64 && 2 * static_cast<uint64_t>(G) <= k && M * G < (1ull << 18)) G <<= 1;
     }
     uint32_t lg = 0;
     while ((1u << lg) < G) ++lg;

@@ -424,72 +424,72 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
   const uint64_t units = static_cast<uint64_t>(A.M) << A.log2G;
   const double kd = static_cast<double>(A.k);
   for (uint64_t tile = blockIdx.x; tile < A.ntiles; tile += gridDim.x) {
-  const uint64_t u0 = tile * A.block_items;
-  const uint64_t u1 = min(u0 + A.block_items, units);
-  for (uint64_t base = u0; base < u1; base += kBlock) {
-    const uint64_t u = base + threadIdx.x;
-    const bool active = u < u1;
-    const uint32_t c = static_cast<uint32_t>(u >> A.log2G);
-    const uint32_t gidx = static_cast<uint32_t>(u) & (G - 1);
-    uint32_t cc[D];
-    {
-      uint32_t r = c;
+    const uint64_t u0 = tile * A.block_items;
+    const uint64_t u1 = min(u0 + A.block_items, units);
+    for (uint64_t base = u0; base < u1; base += kBlock) {
+      const uint64_t u = base + threadIdx.x;
+      const bool active = u < u1;
+      const uint32_t c = static_cast<uint32_t>(u >> A.log2G);
+      const uint32_t gidx = static_cast<uint32_t>(u) & (G - 1);
+      uint32_t cc[D];
+      {
+        uint32_t r = c;
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const uint32_t q = r / A.ng;
-        cc[a] = r - q * A.ng;
-        r = q;
+        for (int a = 0; a < D; ++a) {
+          const uint32_t q = r / A.ng;
+          cc[a] = r - q * A.ng;
+          r = q;
+        }
+      }
+      const uint32_t t0 = active ? static_cast<uint32_t>((static_cast<uint64_t>(gidx) * A.k) >> A.log2G) : 0u;
+      const uint32_t t1 =
+          active ? static_cast<uint32_t>((static_cast<uint64_t>(gidx + 1) * A.k) >> A.log2G) : 0u;
+      double c1 = 0.0, c2 = 0.0, cm = 0.0;
+      double cg1[NG + 1], cg2[NG + 1];
+#pragma unroll
+      for (int q = 0; q < NG; ++q) cg1[q] = cg2[q] = 0.0;
+      for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t s = c + t * A.M;
+        uint32_t w[D];
+        sample_words<D>(s, A.it, A.kid, A.key, w);
+        int j[D];
+        T x[D], jac;
+        make_point<T, D, true>(A, tab, w, cc, j, x, jac);
+        T g[F::NGRAD + 1];
+        const T fv = fn.template eval<GRAD>(x, g);
+        accumulate<F, KIND>(A, hist, j, fv, jac, g, acc, cnt);
+        if (FWD) {
+          const double wd = static_cast<double>(fv * jac);
+          c1 += wd;
+          c2 += wd * wd;
+          if (CMAX) cm = fmax(cm, wd);  // a NaN weight never becomes the maximum
+        }
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+          const double gq = static_cast<double>(g[q] * jac);
+          cg1[q] += gq;
+          cg2[q] += gq * gq;
+        }
+      }
+      for (uint32_t off = 1; off < G; off <<= 1) {
+        if (FWD) {
+          c1 += __shfl_xor(c1, off, kWave);
+          c2 += __shfl_xor(c2, off, kWave);
+        }
+        if (CMAX) cm = fmax(cm, __shfl_xor(cm, off, kWave));
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+          cg1[q] += __shfl_xor(cg1[q], off, kWave);
+          cg2[q] += __shfl_xor(cg2[q], off, kWave);
+        }
+      }
+      if (active && gidx == 0) {
+        if (FWD) acc[kA0 + 2 * NG] += kd * c2 - c1 * c1;
+        if (CMAX && cm > A.cube_max[c]) A.cube_max[c] = cm;  // one writer per cube and launch
+#pragma unroll
+        for (int q = 0; q < NG; ++q) acc[kA0 + 1 + 2 * NG + q] += kd * cg2[q] - cg1[q] * cg1[q];
       }
     }
-    const uint32_t t0 = active ? static_cast<uint32_t>((static_cast<uint64_t>(gidx) * A.k) >> A.log2G) : 0u;
-    const uint32_t t1 =
-        active ? static_cast<uint32_t>((static_cast<uint64_t>(gidx + 1) * A.k) >> A.log2G) : 0u;
-    double c1 = 0.0, c2 = 0.0, cm = 0.0;
-    double cg1[NG + 1], cg2[NG + 1];
-#pragma unroll
-    for (int q = 0; q < NG; ++q) cg1[q] = cg2[q] = 0.0;
-    for (uint32_t t = t0; t < t1; ++t) {
-      const uint32_t s = c + t * A.M;
-      uint32_t w[D];
-      sample_words<D>(s, A.it, A.kid, A.key, w);
-      int j[D];
-      T x[D], jac;
-      make_point<T, D, true>(A, tab, w, cc, j, x, jac);
-      T g[F::NGRAD + 1];
-      const T fv = fn.template eval<GRAD>(x, g);
-      accumulate<F, KIND>(A, hist, j, fv, jac, g, acc, cnt);
-      if (FWD) {
-        const double wd = static_cast<double>(fv * jac);
-        c1 += wd;
-        c2 += wd * wd;
-        if (CMAX) cm = fmax(cm, wd);  // a NaN weight never becomes the maximum
-      }
-#pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        const double gq = static_cast<double>(g[q] * jac);
-        cg1[q] += gq;
-        cg2[q] += gq * gq;
-      }
-    }
-    for (uint32_t off = 1; off < G; off <<= 1) {
-      if (FWD) {
-        c1 += __shfl_xor(c1, off, kWave);
-        c2 += __shfl_xor(c2, off, kWave);
-      }
-      if (CMAX) cm = fmax(cm, __shfl_xor(cm, off, kWave));
-#pragma unroll
-      for (int q = 0; q < NG; ++q) {
-        cg1[q] += __shfl_xor(cg1[q], off, kWave);
-        cg2[q] += __shfl_xor(cg2[q], off, kWave);
-      }
-    }
-    if (active && gidx == 0) {
-      if (FWD) acc[kA0 + 2 * NG] += kd * c2 - c1 * c1;
-      if (CMAX && cm > A.cube_max[c]) A.cube_max[c] = cm;  // one writer per cube and launch
-#pragma unroll
-      for (int q = 0; q < NG; ++q) acc[kA0 + 1 + 2 * NG + q] += kd * cg2[q] - cg1[q] * cg1[q];
-    }
-  }
   }
   acc[2] = static_cast<double>(cnt[0]);
   acc[3] = static_cast<double>(cnt[1]);

@@ -61,6 +61,18 @@ CONFIGS = {w.name: w for w in (C1, C2, C2_PLAIN, C3, C4, C6)}
 DEFAULT_BENCH = C4
 
 
+def default_ng(ncall: int, dim: int, nbins: int) -> int:
+    """BASES stratification when none is given: the largest divisor of nbins
+    not above (ncall / 2)^(1/dim), so that every cube gets at least two
+    samples (at least 2)."""
+    top = int((ncall / 2) ** (1.0 / dim) + 1e-9)
+    best = 2
+    for ng in range(2, max(top, 2) + 1):
+        if nbins % ng == 0:
+            best = ng
+    return best
+
+
 def ngrad(w) -> int:
     """Number of differentiable parameters of a workload's integrand."""
     return {CONST: 1, LINEAR: 0, GAUSS: 2, DGAUSS: 3, GAUSS_AXES: w.dim + 1, WJETS: 3, PSVOL: 0,
