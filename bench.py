@@ -419,6 +419,16 @@ def main(argv=None):
             "frac_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
             "kernel": "sample-and-accumulate (forward)", "avg_launch_ms": avg_ms, "launches": m["nl"],
             "flops_per_sample": flops, "accepted_fraction": frac_pass, "samples_per_launch": n_eff}
+    # LDS atomic throughput of the histogram step against the measured peak
+    from paper_1010_2107_amd import _lib as L
+    import ctypes
+    peak = ctypes.c_double()
+    L.call("vmc_probe_lds_atomics", 2048, 4096, ctypes.byref(peak),
+           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    lds_achieved = 2 * w.dim * n_eff / (avg_ms / 1e3)
+    roof["lds_atomics"] = {"achieved_per_s": lds_achieved, "peak_per_s": peak.value,
+                           "frac": lds_achieved / peak.value,
+                           "note": "2 dim FP64 LDS adds per sample; peak from a conflict-free probe kernel"}
     line = {
         "metric": "integrand evals/s (fwd)", "value": m["value"], "unit": "evals/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": m["ms"] / steps, "higher_is_better": True, "scaling": "weak",

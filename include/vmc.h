@@ -229,6 +229,13 @@ int vmc_set_schedule(vmc_grid_t g, int block_samples, int chunks_per_cube);
  * or disables recording.  Errors: VMC_E_INVALID, VMC_E_HIP. */
 int vmc_timing(vmc_grid_t g, int enable, double *total_ms, int64_t *launches);
 
+/* Calibration: the chip's LDS FP64 atomic-add rate (adds per second) with
+ * one LDS double per lane and 8 independent adds per loop trip, `blocks`
+ * blocks of 256 threads, `iters` trips.  Waits for the stream.  It bounds
+ * the per-bin histogram step of the sample pass (Sec. 3.1 step 4: 2 dim LDS
+ * atomics per sample).  Errors: VMC_E_INVALID, VMC_E_HIP. */
+int vmc_probe_lds_atomics(int blocks, int iters, double *rate, void *stream);
+
 /* ------------------------------------------------------------ batches */
 /* Many independent integrals of uneven dimension and call count advanced
  * together by one persistent launch per iteration.  Integral k has its own
