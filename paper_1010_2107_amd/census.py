@@ -1,13 +1,13 @@
 """FP32 flop census of one sample of the sample-and-accumulate kernel.
 
 Counts the FP32 operations of the per-sample algorithm as written in the HIP
-sources (add/sub/mul = 1, fma = 2; a division or a transcendental counts 1
-flop and is also tallied in `trans`; integer work, compares and the FP64
-accumulation are not FP32 flops).  The W + partons integrand has two paths:
+sources (add/sub/mul = 1, fma = 2).  Reciprocals, square roots and other
+transcendentals are tallied in `trans` and are not counted as flops; integer
+work, compares, min/max and the FP64 accumulation are not FP32 flops either.  The W + partons integrand has two paths:
 samples that fail the cuts stop before the colour sum; `per_sample(...)`
 returns both and the bench weights them with the measured accepted fraction.
-Where the kernel evaluates a choice both ways (the two Newton branches of
-the mass step), only the branch the algorithm needs is counted.
+Where the kernel evaluates a choice both ways (the two sides of the mass
+step's start), only the side the algorithm needs is counted.
 """
 from __future__ import annotations
 
@@ -49,13 +49,21 @@ def cycle_sum_flops(m):
 MAP_PER_AXIS = 5  # delta scale, fma(delta, width, lo), width*N, Jacobian product
 
 
-def _newton_branch_avg(K):
+MASS_START_DEG = 5  # degree of the fitted start polynomial (csrc/vmc_mass_start.hpp)
+
+
+def _mass_step(K):
+    """Flops and transcendentals of one mass-fraction solve.  K = 1 is in
+    closed form.  Otherwise: the start on the lane's side (two scalings and
+    log2/exp2, or 1 - r, a scaling and a square root), the correction
+    polynomial and its product with s, one Newton step on v^2 H(v) - target
+    (H and H' by Horner, the residual, the derivative, a reciprocal and the
+    update), and 1 - v."""
     if K == 1:
         return 3, 2
-    iters = 4
-    b1 = 2 + iters * (K + 9) + 1  # start (r/k1, /k)... then K-1+1+3+3+3 per step
-    b2 = 3 + iters * (4 * (K - 1) + 6) + 1
-    return (b1 + b2) / 2.0, 3 + 2 * iters  # flops, trans (start + one division per step)
+    start = 2.5 + 2 * MASS_START_DEG + 1
+    step = 2 * (K - 1) + 2 * (K - 2) + 1 + 2 + 1 + 2 + 1 + 1 + 1
+    return start + step + 1, 1.5 + 1
 
 
 def wjets(n_p: int) -> Census:
@@ -69,7 +77,7 @@ def wjets(n_p: int) -> Census:
     t += 4
     # mass chain: one inverse-CDF solve per mass, then M_i = M_{i-1} sqrt(t)
     for K in range(n - 2, 0, -1):
-        ff, tt = _newton_branch_avg(K)
+        ff, tt = _mass_step(K)
         f += ff + 1
         t += tt + 1
     # two-body steps: the first needs no boost, the others boost two vectors
@@ -98,7 +106,7 @@ def whel(n: int) -> Census:
     f += 17
     t += 4
     for K in range(nf - 2, 0, -1):  # mass chain
-        ff, tt = _newton_branch_avg(K)
+        ff, tt = _mass_step(K)
         f += ff + 1
         t += tt + 1
     f += 17 + (nf - 2) * 52  # two-body steps and boosts

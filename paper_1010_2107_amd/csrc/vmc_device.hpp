@@ -23,26 +23,9 @@ struct Key {
   uint32_t k0, k1;
 };
 
-__device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, Key key,
-                                         uint32_t (&out)[4]) {
-  uint32_t k0 = key.k0, k1 = key.k1;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
-    const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
-    const uint32_t x0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ k0;
-    const uint32_t x2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ k1;
-    c1 = static_cast<uint32_t>(pb);
-    c3 = static_cast<uint32_t>(pa);
-    c0 = x0;
-    c2 = x2;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-  out[0] = c0;
-  out[1] = c1;
-  out[2] = c2;
-  out[3] = c3;
+// a ^ b ^ c in one v_bitop3_b32 (truth table 0x96); c may be a scalar.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
 // Rounds 2-10 of Philox4x32-10 given the first round's products.
@@ -59,8 +42,8 @@ __device__ __forceinline__ void philox10_from_round1(uint32_t hi0, uint32_t lo0,
     k1 += 0xBB67AE85u;
     const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
     const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
-    const uint32_t x0 = static_cast<uint32_t>(pb >> 32) ^ c1 ^ k0;
-    const uint32_t x2 = static_cast<uint32_t>(pa >> 32) ^ c3 ^ k1;
+    const uint32_t x0 = xor3(static_cast<uint32_t>(pb >> 32), c1, k0);
+    const uint32_t x2 = xor3(static_cast<uint32_t>(pa >> 32), c3, k1);
     c1 = static_cast<uint32_t>(pb);
     c3 = static_cast<uint32_t>(pa);
     c0 = x0;
@@ -162,6 +145,10 @@ __device__ __forceinline__ float vexp_fast(float x) { return __builtin_amdgcn_ex
 __device__ __forceinline__ double vexp_fast(double x) { return exp(x); }
 __device__ __forceinline__ float vlog_fast(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
 __device__ __forceinline__ double vlog_fast(double x) { return log(x); }
+__device__ __forceinline__ float vlog2_fast(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ double vlog2_fast(double x) { return log2(x); }
+__device__ __forceinline__ float vexp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ double vexp2_fast(double x) { return exp2(x); }
 // sin and cos of 2 pi x for x in [0, 1): the hardware takes its argument in
 // revolutions (absolute error ~1e-7 in FP32).
 __device__ __forceinline__ void vsincos2pi(float x, float& s, float& c) {

@@ -142,7 +142,7 @@ struct StagedTraits<F, std::void_t<decltype(F::kStaged)>> {
   static constexpr bool value = F::kStaged;
   static constexpr int words = F::kStateWords;
 };
-constexpr int kQueueCap = 2 * kWave;  // entries per wave: up to 63 waiting + 64 new
+constexpr int kQueueCap = kWave;  // entries per wave (at most 63 wait between runs)
 // queue words per entry: the state, the Jacobian and the bin indices (4 per word)
 template <class F>
 constexpr int queue_words() {
@@ -310,69 +310,81 @@ __global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
 
   const uint32_t dummy_cc[D] = {};
   if constexpr (StagedTraits<F>::value) {
-    // per-wave LDS queue (structure of arrays) of samples that passed stage 1
+    // Per-wave LDS queue (structure of arrays) of samples that passed stage 1.
+    // When the waiting and the newly passed samples make a full wave, every
+    // lane runs stage 2 once: a lane that passed on its own sample, any other
+    // lane on the newest queued one.  Otherwise the passed samples join the
+    // queue, which therefore never holds more than 63.
     constexpr int NQ = queue_words<F>();
     constexpr int NS = StagedTraits<F>::words;
+    constexpr int NPK = (D + 3) / 4;  // bin indices, four per word
+    using State = typename F::State;
     const int lane = threadIdx.x & (kWave - 1);
     // after the histogram (forward passes) or right after the table
     float* q = reinterpret_cast<float*>(hist + ((KIND & KIND_FWD) ? 2 * D * A.nbins : 0)) +
                (threadIdx.x / kWave) * NQ * kQueueCap;
     uint32_t* qj = reinterpret_cast<uint32_t*>(q + (NS + 1) * kQueueCap);
-    int qn = 0;  // entries waiting (wave-uniform)
-    auto run = [&](int e) {
-      const typename F::State st = F::load_state(q, kQueueCap, e);
-      const T jac = static_cast<T>(q[NS * kQueueCap + e]);
+    auto push = [&](int e, const State& st, T jac, const uint32_t (&pk)[NPK]) {
+      F::store_state(st, q, kQueueCap, e);
+      q[NS * kQueueCap + e] = static_cast<float>(jac);
+#pragma unroll
+      for (int w = 0; w < NPK; ++w) qj[w * kQueueCap + e] = pk[w];
+    };
+    auto pop = [&](int e, State& st, T& jac, uint32_t (&pk)[NPK]) {
+      st = F::load_state(q, kQueueCap, e);
+      jac = static_cast<T>(q[NS * kQueueCap + e]);
+#pragma unroll
+      for (int w = 0; w < NPK; ++w) pk[w] = qj[w * kQueueCap + e];
+    };
+    auto run = [&](const State& st, T jac, const uint32_t (&pk)[NPK]) {
       int j[D];
 #pragma unroll
-      for (int a = 0; a < D; a += 4) {
-        const uint32_t pk = qj[(a / 4) * kQueueCap + e];
-#pragma unroll
-        for (int b = 0; b < 4 && a + b < D; ++b) j[a + b] = static_cast<int>((pk >> (8 * b)) & 0xFFu);
-      }
+      for (int a = 0; a < D; ++a) j[a] = static_cast<int>((pk[a / 4] >> (8 * (a % 4))) & 0xFFu);
       T g[F::NGRAD + 1];
       const T fv = fn.template stage2<(KIND & KIND_ADJ) != 0>(st, g);
       accumulate<F, KIND>(A, hist, j, fv, jac, g, acc, cnt);
     };
+    int qn = 0;  // entries waiting (wave-uniform)
     for (uint64_t t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
       const uint64_t b0 = t * A.block_items;
       const uint64_t b1 = min(b0 + A.block_items, A.ncall);
       for (uint64_t base = b0; base < b1; base += kBlock) {
         const uint64_t s = base + threadIdx.x;
         bool pass = false;
-        typename F::State st;
-        int j[D];
+        State st;
+        uint32_t pk[NPK] = {};
         T jac = T(0);
         if (s < b1) {
           uint32_t w[D];
           sample_words<D>(static_cast<uint32_t>(s), A.it, A.kid, A.key, w);
           T x[D];
+          int j[D];
           make_point<T, D, false>(A, tab, w, dummy_cc, j, x, jac);
           pass = fn.stage1(x, st);
           cnt[1] += pass ? 0u : 1u;  // f = 0 outside the cuts: nothing else to add
+#pragma unroll
+          for (int a = 0; a < D; ++a) pk[a / 4] |= static_cast<uint32_t>(j[a]) << (8 * (a % 4));
         }
         const uint64_t m = __ballot(pass);
-        if (pass) {
-          const int e = qn + static_cast<int>(__popcll(m & __lanemask_lt()));
-          F::store_state(st, q, kQueueCap, e);
-          q[NS * kQueueCap + e] = static_cast<float>(jac);
-#pragma unroll
-          for (int a = 0; a < D; a += 4) {
-            uint32_t pk = 0;
-#pragma unroll
-            for (int b = 0; b < 4 && a + b < D; ++b) pk |= static_cast<uint32_t>(j[a + b]) << (8 * b);
-            qj[(a / 4) * kQueueCap + e] = pk;
-          }
+        const int np = static_cast<int>(__popcll(m));
+        if (qn + np >= kWave) {
+          if (!pass) pop(qn - 1 - static_cast<int>(__popcll(~m & __lanemask_lt())), st, jac, pk);
+          run(st, jac, pk);
+          qn -= kWave - np;
+        } else {
+          if (pass) push(qn + static_cast<int>(__popcll(m & __lanemask_lt())), st, jac, pk);
+          qn += np;
         }
-        qn += static_cast<int>(__popcll(m));
         __builtin_amdgcn_wave_barrier();
-        if (qn >= kWave) {  // a full wave of queued samples: the newest 64
-          qn -= kWave;
-          run(qn + lane);
-          __builtin_amdgcn_wave_barrier();
-        }
       }
     }
-    if (lane < qn) run(lane);
+    if (lane < qn) {
+      State st;
+      T jac;
+      uint32_t pk[NPK];
+      pop(lane, st, jac, pk);
+      run(st, jac, pk);
+    }
   } else {
     for (uint64_t t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
       const uint64_t b0 = t * A.block_items;

@@ -23,6 +23,7 @@
 #pragma once
 
 #include "vmc_device.hpp"
+#include "vmc_mass_start.hpp"
 
 namespace vmc {
 
@@ -72,10 +73,15 @@ __device__ __forceinline__ T cycle_sum(const T (&y)[M][M]) {
 
 // ---------------------------------------------------------------------------
 // Mass step of RAMBO on diet: the fraction t = M_i^2 / M_{i-1}^2 has CDF
-// F(t) = (k+1) t^k - k t^(k+1), k = n - i.  Inverted by Newton's method: on
-// t for r < 1/2 (start from F ~ (k+1) t^k), and on u = 1 - t otherwise,
-// using 1 - F(1-u) as a polynomial in u without the cancelling low-order
-// terms (start from 1 - F ~ k(k+1) u^2 / 2).  Returns t and u = 1 - t.
+// F(t) = (k+1) t^k - k t^(k+1), k = n - i.  The inversion F(t) = r works on
+// v = t for r < 1/2 and on v = u = 1 - t otherwise.  On the high side the
+// residual is (1 - F(1-u)) - (1 - r), with 1 - F(1-u) written as a
+// polynomial in u that starts at u^2, so that no low-order terms cancel.
+// On both sides the residual is v^2 H(v) - target, H of degree k-1, and each
+// lane picks its coefficients once.  The start inverts the leading term and
+// corrects it with a fitted polynomial (vmc_mass_start.hpp); its relative
+// error is below 1.5e-4, so one Newton step reaches FP32 round-off and
+// three reach FP64 round-off.  Returns t and u = 1 - t.
 // ---------------------------------------------------------------------------
 template <int K>
 constexpr double binom(int n, int j) {
@@ -93,6 +99,12 @@ constexpr double comp_coef(int j) {
   return c;
 }
 
+// coefficient of t^(j+2) in F(t)
+template <int K>
+constexpr double low_coef(int j) {
+  return j == K - 2 ? K + 1.0 : (j == K - 1 ? -static_cast<double>(K) : 0.0);
+}
+
 template <typename T>
 struct TU {
   T t, u;
@@ -104,33 +116,38 @@ __device__ __forceinline__ TU<T> mass_fraction(T r) {
     const T s = vsqrt(T(1) - r);
     return TU<T>{r * vrcp(T(1) + s), s};
   } else {
-    constexpr int ITERS = sizeof(T) == 4 ? 4 : 6;
-    const T k1 = T(K + 1), kk = T(K);
+    static_assert(K >= kMassStartMinK && K <= kMassStartMaxK, "no start polynomial for this k");
+    constexpr int ITERS = sizeof(T) == 4 ? 1 : 3;
+    constexpr int row = K - kMassStartMinK;
     const bool lo = r < T(0.5);
     const T q = T(1) - r;  // exact for r >= 1/2
-    // start: F ~ (k+1) t^k for small t, 1 - F ~ k(k+1) u^2 / 2 for small u
-    const T ts = r > T(0) ? vexp_fast(vlog_fast(r * T(1.0 / (K + 1))) * T(1.0 / K)) : T(0);
-    const T us = vsqrt(q * T(2.0 / (K * (K + 1))));
-    T t = lo ? ts : T(1) - us;
-    T u = lo ? T(1) - ts : us;
+    // s = (r / (K+1))^(1/K) or (2 q / (K (K+1)))^(1/2), one log2 and one exp2
+    const T a = lo ? r * T(1.0 / (K + 1)) : q * T(2.0 / (K * (K + 1)));
+    const T s = a > T(0) ? vexp2_fast(vlog2_fast(a) * (lo ? T(1.0 / K) : T(0.5))) : T(0);
+    T rl = T(kMassStartLo[row][kMassStartDeg]), rh = T(kMassStartHi[row][kMassStartDeg]);
+#pragma unroll
+    for (int j = kMassStartDeg - 1; j >= 0; --j) {
+      rl = fma(rl, s, T(kMassStartLo[row][j]));
+      rh = fma(rh, s, T(kMassStartHi[row][j]));
+    }
+    T v = fmin(s * (lo ? rl : rh), T(1));
+    const T target = lo ? r : q;
+    T h[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) h[j] = lo ? T(low_coef<K>(j)) : T(comp_coef<K>(j + 2));
 #pragma unroll
     for (int it = 0; it < ITERS; ++it) {
-      T tk1 = T(1);
+      T H = h[K - 1], Hd = T(0);
 #pragma unroll
-      for (int j = 0; j < K - 1; ++j) tk1 *= t;
-      // residual F(t) - r, from t where t is small and as (1-r) - (1-F(1-u))
-      // from u otherwise; 1 - F(1-u) is a polynomial in u starting at u^2
-      T G = T(comp_coef<K>(K + 1));
-#pragma unroll
-      for (int j = K; j >= 2; --j) G = fma(G, u, T(comp_coef<K>(j)));
-      G *= u * u;
-      const T res = lo ? fma(tk1 * t, k1 - kk * t, -r) : q - G;
-      const T dF = (kk * k1) * tk1 * u;
-      const T step = dF > T(0) ? res * vrcp(dF) : T(0);
-      t = fmin(fmax(t - step, T(0)), T(1));
-      u = fmin(fmax(u + step, T(0)), T(1));
+      for (int j = K - 2; j >= 0; --j) {
+        Hd = fma(Hd, v, H);
+        H = fma(H, v, h[j]);
+      }
+      const T res = fma(v * v, H, -target);
+      const T dP = v * fma(v, Hd, T(2) * H);  // > 0 inside (0, 1]; 0 at v = 0 where res = 0
+      v = fmin(fmax(v - res * vrcp(fmax(dP, T(1e-30))), T(0)), T(1));
     }
-    return TU<T>{t, u};
+    return lo ? TU<T>{v, T(1) - v} : TU<T>{T(1) - v, v};
   }
 }
 
