@@ -72,8 +72,9 @@ def wjets(n_p: int) -> Census:
     nv = n_p + 1
     f = t = 0
     f += MAP_PER_AXIS * D
-    # parton fractions, flux x Jacobian, s^(n-3), boost rapidity
-    f += 17 + (n - 3)
+    # parton fractions, flux x Jacobian, s^(n-3), boost rapidity; each
+    # e^x - 1 counted on its exp2 side (a scaling and a subtraction)
+    f += 21 + (n - 3)
     t += 4
     # mass chain: one inverse-CDF solve per mass, then M_i = M_{i-1} sqrt(t)
     for K in range(n - 2, 0, -1):
@@ -86,8 +87,8 @@ def wjets(n_p: int) -> Census:
     # visible particles: pT^2, light-cone components, rapidity, pT, cuts
     f += 8 * nv
     t += 4 * nv
-    # Delta R pairs: cos of the threshold angle by a 6-term Horner series
-    f += 20 * nv * (nv - 1) // 2
+    # Delta R pairs: cos of the threshold angle by a 4-term Horner series
+    f += 18 * nv * (nv - 1) // 2
     f_fail, t_fail = f + 1, t
     # accepted samples: scaled invariants, cyclic sum, Breit-Wigner, product
     m = n_p + 2
@@ -103,7 +104,7 @@ def whel(n: int) -> Census:
     D = 3 * n + 5
     f = t = 0
     f += MAP_PER_AXIS * D
-    f += 17
+    f += 21  # parton fractions and flux x Jacobian, as for wjets
     t += 4
     for K in range(nf - 2, 0, -1):  # mass chain
         ff, tt = _mass_step(K)

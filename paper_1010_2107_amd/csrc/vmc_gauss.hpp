@@ -70,7 +70,7 @@ struct Peak {
       q = fma(t, t, q);
       if (GRAD) l += t;
     }
-    const T f = vexp(fma(-q, inv_s2, log_norm));
+    const T f = vexp_fast(fma(-q, inv_s2, log_norm));
     if (GRAD) {
       dlc = fma(two_inv_s2, l, -kc);
       dls = fma(two_inv_s3, q, -ks);
@@ -147,7 +147,7 @@ struct GaussAxesF {
       t[a] = x[a] - c[a];
       q = fma(t[a], t[a], q);
     }
-    const T f = vexp(fma(-q, inv_s2, log_norm));
+    const T f = vexp_fast(fma(-q, inv_s2, log_norm));
     if (GRAD) {
       const T f2 = f * two_inv_s2;
 #pragma unroll

@@ -192,10 +192,10 @@ struct WHelF {
   __device__ __forceinline__ bool stage1(const T (&x)[D], State& st) const {
     const T la = L * (T(1) - x[0]);
     const T lb = L * x[0] * (T(1) - x[1]);
-    const T h = vexp(T(0.5) * (la + lb));  // sqrt(tau)
+    const T h = vexp2_fast((la + lb) * T(0.5 * 1.4426950408889634));  // sqrt(tau)
     const T rs = sqrtS * h;
     const T shat = rs * rs;
-    const T om = vexpm1(la) * vexpm1(lb);
+    const T om = vexpm1_fast(la) * vexpm1_fast(lb);
     const T fluxjac = LL * x[0] * (om * om * om) * vrcp(h);
     const T yb = T(0.5) * (la - lb);
     T Mi[NOUT + 1], Ui[NOUT + 1];
