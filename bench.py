@@ -23,13 +23,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 def source_sha1():
-    """Hash of the kernel sources and the public header, identifying the
+    """Hash of the sources the sample kernels are built from (device headers,
+    the integrand instantiations and the launch code), identifying the
     kernel build that a hardware-counter summary was taken on."""
     import glob
     import hashlib
     h = hashlib.sha1()
-    files = sorted(glob.glob(os.path.join(ROOT, "paper_1010_2107_amd", "csrc", "*"))) + [
-        os.path.join(ROOT, "include", "vmc.h")]
+    csrc = os.path.join(ROOT, "paper_1010_2107_amd", "csrc")
+    files = sorted(glob.glob(os.path.join(csrc, "*.hpp")) + glob.glob(os.path.join(csrc, "inst_*.hip")) +
+                   [os.path.join(csrc, "vmc_capi.hip")])
     for f in files:
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode())
@@ -59,7 +61,6 @@ def measured_traffic(workload_name):
 
 
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (packed FMA): 256 CU x 2.4 GHz x 256 flop/clk
-PEAK_FP32_NONPACKED = 78.6   # the same without packed FP32 (this build disables packed FP32)
 
 
 def run_loop(grid, w, steps, adjoint=False, fused=False):
@@ -416,15 +417,19 @@ def main(argv=None):
     achieved = flops * n_eff / (avg_ms / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(w.name),
-            "frac_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
             "kernel": "sample-and-accumulate (forward)", "avg_launch_ms": avg_ms, "launches": m["nl"],
             "flops_per_sample": flops, "accepted_fraction": frac_pass, "samples_per_launch": n_eff}
-    # LDS atomic throughput of the histogram step against the measured peak
+    # the kernel against the rates probe kernels measure on this chip: FP32 FMA
+    # issue (packed FP32 off, at the clock held under load) and LDS FP64 adds
     from paper_1010_2107_amd import _lib as L
     import ctypes
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    fma = ctypes.c_double()
+    L.call("vmc_probe_fp32_fma", 8192, 4096, ctypes.byref(fma), stream)
+    roof["fp32_fma_probe"] = {"peak_tflops": fma.value / 1e12, "frac": achieved / (fma.value / 1e12),
+                              "note": "8 independent FP32 FMA chains per lane, packed FP32 off"}
     peak = ctypes.c_double()
-    L.call("vmc_probe_lds_atomics", 2048, 4096, ctypes.byref(peak),
-           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    L.call("vmc_probe_lds_atomics", 2048, 4096, ctypes.byref(peak), stream)
     lds_achieved = 2 * w.dim * n_eff / (avg_ms / 1e3)
     roof["lds_atomics"] = {"achieved_per_s": lds_achieved, "peak_per_s": peak.value,
                            "frac": lds_achieved / peak.value,

@@ -236,6 +236,13 @@ int vmc_timing(vmc_grid_t g, int enable, double *total_ms, int64_t *launches);
  * atomics per sample).  Errors: VMC_E_INVALID, VMC_E_HIP. */
 int vmc_probe_lds_atomics(int blocks, int iters, double *rate, void *stream);
 
+/* Calibration: the chip's sustained FP32 fused multiply-add rate (flops per
+ * second, 2 per FMA) with 8 independent FMA chains per lane, `blocks`
+ * blocks of 256 threads, `iters` trips, at the clock the chip holds under
+ * that load.  Waits for the stream.  It bounds the integrand arithmetic of
+ * the sample pass (Sec. 3.1 step 3).  Errors: VMC_E_INVALID, VMC_E_HIP. */
+int vmc_probe_fp32_fma(int blocks, int iters, double *flops, void *stream);
+
 /* ------------------------------------------------------------ batches */
 /* Many independent integrals of uneven dimension and call count advanced
  * together by one persistent launch per iteration.  Integral k has its own

@@ -78,6 +78,7 @@ _SIGS = {
     "vmc_batch_combine_reset": (_c.c_int, [_vp, _vp]),
     "vmc_batch_timing": (_c.c_int, [_vp, _c.c_int, _c.POINTER(_c.c_double), _c.POINTER(_c.c_int64)]),
     "vmc_probe_lds_atomics": (_c.c_int, [_c.c_int, _c.c_int, _c.POINTER(_c.c_double), _vp]),
+    "vmc_probe_fp32_fma": (_c.c_int, [_c.c_int, _c.c_int, _c.POINTER(_c.c_double), _vp]),
     "bases_cube_max": (_c.c_int, [_vp, _vp, _c.c_int64]),
     "spring_workspace_sizes": (_c.c_int, [_vp, _c.POINTER(_c.c_size_t)]),
     "spring_setup": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
