@@ -153,7 +153,9 @@ constexpr int queue_bytes() {
   return StagedTraits<F>::value ? (kBlock / kWave) * kQueueCap * queue_words<F>() * 4 : 0;
 }
 
-// LDS layout: grid table first (16-byte entries for FP64), then histogram.
+// LDS layout: grid table first (16-byte entries for FP64), then the histogram
+// [2][d][N] (adjacent bins 8 bytes apart, so a wave's random bins spread
+// over the LDS banks).
 template <typename T, int D>
 __device__ __forceinline__ void load_table(const SampleArgs& A, typename TabEntry<T>::type* tab) {
   const int n = D * static_cast<int>(A.nbins);
@@ -207,10 +209,12 @@ __device__ __forceinline__ void accumulate(const SampleArgs& A, double* hist, co
     acc[1] += wd * wd;
     cnt[0] += vfinite(wv) ? 0u : 1u;
     cnt[1] += (wv == 0) ? 1u : 0u;
+    const int dn = D * N;  // sum w^2 sits one axis set after sum w
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      lds_add(&hist[a * N + j[a]], wd);
-      lds_add(&hist[(D + a) * N + j[a]], wd * wd);
+      double* h = &hist[a * N + j[a]];
+      lds_add(h, wd);
+      lds_add(h + dn, wd * wd);
     }
   }
   if (GRAD) {
@@ -356,7 +360,12 @@ __global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
         T jac = T(0);
         if (s < b1) {
           uint32_t w[D];
-          sample_words<D>(static_cast<uint32_t>(s), A.it, A.kid, A.key, w);
+          // The round keys are recomputed per sample in scalar registers
+          // rather than held across the loop, where they crowd the scalar
+          // register file into spills.
+          Key key = A.key;
+          asm volatile("" : "+s"(key.k0), "+s"(key.k1));
+          sample_words<D>(static_cast<uint32_t>(s), A.it, A.kid, key, w);
           T x[D];
           int j[D];
           make_point<T, D, false>(A, tab, w, dummy_cc, j, x, jac);
