@@ -107,21 +107,27 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& B, const BatchDesc& 
                                            double (&acc)[NACC], uint32_t (&cnt)[2]) {
   constexpr bool FWD = KIND & KIND_FWD, GRAD = KIND & KIND_ADJ;
   const int N = static_cast<int>(B.nbins);
-  const T Nf = static_cast<T>(N);
+  const T Nk = static_cast<T>(N) * static_cast<T>(1.0 / kWidthScale);
+  const T Nk2 = Nk * Nk;
   const GaussAxesF<T, D> fn = block_setup<GaussAxesF<T, D>>(B.theta + ds.off_theta);
   for (uint32_t s = tl.s0 + threadIdx.x; s < tl.s1; s += kBlock) {
     uint32_t w[D];
     sample_words<D>(s, B.it, ds.kid, B.key, w);
     int j[D];
     T x[D];
-    T jac = T(1);
+    T jac = T(1), wprev = T(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      T dl;
-      bin_plain<T>(w[a], B.nbins, j[a], dl);
+      T off;
+      bin_plain<T>(w[a], B.nbins, j[a], off);
       const auto e = tab[a * N + j[a]];
-      x[a] = fma(dl, e.y, e.x);
-      jac *= e.y * Nf;
+      x[a] = fma(off, e.y, e.x);
+      if (a & 1) {
+        jac *= (wprev * e.y) * Nk2;
+      } else if (a == D - 1) {
+        jac *= e.y * Nk;
+      }
+      wprev = e.y;
     }
     T g[D + 2];
     const T fv = fn.template eval<GRAD>(x, g);
@@ -184,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_batched(const BatchArgs B) {
         } else {
           const int a = i / N, jb = i - a * N;
           const double* e = B.edges + ds.off_edges + static_cast<size_t>(a) * (N + 1);
-          tab[i] = make_double2(e[jb], e[jb + 1] - e[jb]);
+          tab[i] = make_double2(e[jb], (e[jb + 1] - e[jb]) * kWidthScale);
         }
       }
       if (FWD)
@@ -269,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_reset(const BatchDesc* desc, u
     const int j = i % N;
     const double lo = static_cast<double>(j) / N, hi = static_cast<double>(j + 1) / N;
     table[ds.off_table + 2 * i] = static_cast<float>(lo);
-    table[ds.off_table + 2 * i + 1] = static_cast<float>(hi - lo);
+    table[ds.off_table + 2 * i + 1] = static_cast<float>((hi - lo) * kWidthScale);
   }
   for (int i = threadIdx.x; i < 2 * d * N; i += kBlock) bins[ds.off_bins + i] = 0.0;
   for (int i = threadIdx.x; i < S_LEN; i += kBlock) scal[ds.off_scal + i] = 0.0;

@@ -89,35 +89,42 @@ __device__ __forceinline__ void sample_words(uint32_t s, uint32_t it, uint32_t k
 // in-bin offset its fraction, both exact in 32-bit integer arithmetic for
 // N <= 256.  Stratified: y = (c + u)/ng, so y N = (c 2^24 + 2m+1) N /
 // (ng 2^24); when ng divides N this is c (N/ng) + (2m+1)(N/ng) 2^-24.
+// The helpers return the offset scaled by 2^24 (an integer below 2^24, exact
+// in FP32), to be multiplied by a width stored times kWidthScale.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ void bin_plain(uint32_t word, uint32_t nbins, int& j, T& delta) {
+__device__ __forceinline__ void bin_plain(uint32_t word, uint32_t nbins, int& j, T& off) {
   // (2m+1) < 2^24 and nbins <= 256: the 24-bit multiply is exact
   const uint32_t P = __umul24(((word >> 9) << 1) | 1u, nbins);
   j = static_cast<int>(P >> 24);
-  delta = static_cast<T>(static_cast<int>(P & 0xFFFFFFu)) * static_cast<T>(5.9604644775390625e-08);
+  off = static_cast<T>(static_cast<int>(P & 0xFFFFFFu));
 }
 
 template <typename T>
-__device__ __forceinline__ void bin_strat_div(uint32_t word, uint32_t ca, uint32_t per_cube, int& j,
-                                              T& delta) {
+__device__ __forceinline__ void bin_strat_div(uint32_t word, uint32_t ca, uint32_t per_cube, int& j, T& off) {
   // ng divides nbins; per_cube = nbins / ng
   const uint32_t P = __umul24(((word >> 9) << 1) | 1u, per_cube);
   j = static_cast<int>(ca * per_cube + (P >> 24));
-  delta = static_cast<T>(static_cast<int>(P & 0xFFFFFFu)) * static_cast<T>(5.9604644775390625e-08);
+  off = static_cast<T>(static_cast<int>(P & 0xFFFFFFu));
 }
 
 template <typename T>
 __device__ __forceinline__ void bin_strat_gen(uint32_t word, uint32_t ca, uint32_t ng, uint32_t nbins,
-                                              int& j, T& delta) {
+                                              int& j, T& off) {
   const uint64_t Q = ((static_cast<uint64_t>(ca) << 24) + ((word >> 9) * 2u + 1u)) * nbins;
   const uint64_t Dn = static_cast<uint64_t>(ng) << 24;
   const uint64_t q = Q / Dn;
   j = static_cast<int>(q);
-  delta = static_cast<T>(static_cast<double>(Q - q * Dn) / static_cast<double>(Dn));
+  off = static_cast<T>(static_cast<double>(Q - q * Dn) / static_cast<double>(Dn) * 16777216.0);
 }
 
-// Grid table entry: lower edge and width of a bin.
+// A grid's table holds per bin the lower edge and the width times
+// kWidthScale = 2^-24, so that a sample's point is fma(off, width', edge) with
+// the offset `off` of the bin helpers: the same value as edge + (off 2^-24)
+// width, since both scalings are exact, one multiply fewer per axis.
+constexpr double kWidthScale = 0x1p-24;
+
+// Grid table entry: lower edge and scaled width of a bin.
 template <typename T>
 struct TabEntry;
 template <>

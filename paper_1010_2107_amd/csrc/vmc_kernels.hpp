@@ -165,7 +165,7 @@ __device__ __forceinline__ void load_table(const SampleArgs& A, typename TabEntr
     } else {
       const int a = i / A.nbins, j = i - a * A.nbins;
       const double* e = A.edges + static_cast<size_t>(a) * (A.nbins + 1);
-      tab[i] = make_double2(e[j], e[j + 1] - e[j]);
+      tab[i] = make_double2(e[j], (e[j + 1] - e[j]) * kWidthScale);
     }
   }
 }
@@ -176,21 +176,30 @@ __device__ __forceinline__ void make_point(const SampleArgs& A, const typename T
                                            const uint32_t (&w)[D], const uint32_t (&cc)[D], int (&j)[D],
                                            T (&x)[D], T& jac) {
   const int N = static_cast<int>(A.nbins);
-  const T Nf = static_cast<T>(N);
+  const T Nk = static_cast<T>(N) * static_cast<T>(1.0 / kWidthScale);  // per-axis Jacobian factor
+  const T Nk2 = Nk * Nk;  // <= 2^64 for N <= 256: exact
   jac = T(1);
+  T wprev = T(0);
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    T dl;
+    T off;
     if (!STRAT) {
-      bin_plain<T>(w[a], A.nbins, j[a], dl);
+      bin_plain<T>(w[a], A.nbins, j[a], off);
     } else if (A.per_cube) {
-      bin_strat_div<T>(w[a], cc[a], A.per_cube, j[a], dl);
+      bin_strat_div<T>(w[a], cc[a], A.per_cube, j[a], off);
     } else {
-      bin_strat_gen<T>(w[a], cc[a], A.ng, A.nbins, j[a], dl);
+      bin_strat_gen<T>(w[a], cc[a], A.ng, A.nbins, j[a], off);
     }
     const auto e = tab[a * N + j[a]];
-    x[a] = fma(dl, e.y, e.x);
-    jac *= e.y * Nf;
+    x[a] = fma(off, e.y, e.x);
+    // J = prod N width, two axes per multiply: a product of two scaled
+    // widths is w_a w_b 2^-48, a normal FP32 number for widths above 2^-39
+    if (a & 1) {
+      jac *= (wprev * e.y) * Nk2;
+    } else if (a == D - 1) {
+      jac *= e.y * Nk;
+    }
+    wprev = e.y;
   }
 }
 

@@ -82,21 +82,22 @@ __global__ __launch_bounds__(kBlock) void k_reset(double* edges, float* table, d
     const double lo = static_cast<double>(j) / static_cast<double>(N);
     const double hi = static_cast<double>(j + 1) / static_cast<double>(N);
     table[2 * i] = static_cast<float>(lo);
-    table[2 * i + 1] = static_cast<float>(hi - lo);
+    table[2 * i + 1] = static_cast<float>((hi - lo) * kWidthScale);
   }
   for (int i = tid; i < nbins_total; i += stride) bins[i] = 0.0;
   for (int i = tid; i < S_LEN; i += stride) scal[i] = 0.0;
 }
 
-// FP32 (lower edge, width) per bin, both rounded from FP64 values (the
-// width is differenced in FP64 first so narrow bins keep their precision).
+// FP32 (lower edge, width x kWidthScale) per bin, both rounded from FP64
+// values (the width is differenced in FP64 first so narrow bins keep their
+// precision).
 __global__ __launch_bounds__(kBlock) void k_table(const double* edges, float* table, int d, int N) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= d * N) return;
   const int a = i / N, j = i - a * N;
   const double* e = edges + static_cast<size_t>(a) * (N + 1);
   table[2 * i] = static_cast<float>(e[j]);
-  table[2 * i + 1] = static_cast<float>(e[j + 1] - e[j]);
+  table[2 * i + 1] = static_cast<float>((e[j + 1] - e[j]) * kWidthScale);
 }
 
 // Refinement of one axis per block (N <= 256 bins, one thread per bin):
@@ -175,7 +176,7 @@ __device__ void refine_axis(double* ea, float* ta, const double* b2, int N, doub
   for (int k = t; k <= N; k += kBlock) ea[k] = en[k];
   for (int j = t; j < N; j += kBlock) {
     ta[2 * j] = static_cast<float>(en[j]);
-    ta[2 * j + 1] = static_cast<float>(en[j + 1] - en[j]);
+    ta[2 * j + 1] = static_cast<float>((en[j + 1] - en[j]) * kWidthScale);
   }
 }
 

@@ -161,7 +161,8 @@ def test_refine_matches_oracle_on_given_bins():
         assert np.max(np.abs(got - ref)) <= 1e-12
         tab = g.table.cpu().numpy()
         assert np.array_equal(tab[..., 0], ref[:, :-1].astype(np.float32))
-        assert np.array_equal(tab[..., 1], np.diff(ref, axis=1).astype(np.float32))
+        # widths are stored times 2^-24 (the bin offset is a 24-bit integer)
+        assert np.array_equal(tab[..., 1], (np.diff(ref, axis=1) * 2.0**-24).astype(np.float32))
 
 
 def test_schedule_invariance():
