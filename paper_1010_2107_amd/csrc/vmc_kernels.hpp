@@ -378,10 +378,10 @@ __global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
           T x[D];
           int j[D];
           make_point<T, D, false>(A, tab, w, dummy_cc, j, x, jac);
-          pass = fn.stage1(x, st);
-          cnt[1] += pass ? 0u : 1u;  // f = 0 outside the cuts: nothing else to add
 #pragma unroll
           for (int a = 0; a < D; ++a) pk[a / 4] |= static_cast<uint32_t>(j[a]) << (8 * (a % 4));
+          pass = fn.stage1(x, st);
+          cnt[1] += pass ? 0u : 1u;  // f = 0 outside the cuts: nothing else to add
         }
         const uint64_t m = __ballot(pass);
         const int np = static_cast<int>(__popcll(m));

@@ -245,7 +245,7 @@ __device__ __forceinline__ LightCone<T> light_cone(const T (&v)[4]) {
   const T ya = vlog_fast(big * rpt);
   r.lp = z > T(0) ? big : small;
   r.lm = z > T(0) ? small : big;
-  r.eta = z > T(0) ? ya : -ya;
+  r.eta = copysign(ya, z);
   r.pt = r.pt2 * rpt;
   r.rpt2 = rpt * rpt;
   return r;
@@ -350,6 +350,7 @@ struct WJetsF {
     constexpr int NV = NP + 1;
     T pt2[NV], pt[NV], rpt2[NV], lp[NV], lm[NV], eta[NV];
     bool pass = true;
+    T pt2_min = T(0);  // the pT cut on the smallest pT^2: one compare instead of NV
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
       const LightCone<T> lc = light_cone(p[j]);
@@ -359,10 +360,16 @@ struct WJetsF {
       lp[j] = lc.lp;
       lm[j] = lc.lm;
       eta[j] = lc.eta;
-      pass = pass && (pt2[j] > ptmin2) && (fabs(eta[j] + yb) < etamax);
+      pt2_min = j == 0 ? pt2[0] : fmin(pt2_min, pt2[j]);
+      // a NaN pT^2 (degenerate momenta) is skipped by fmin, but its rapidity
+      // is NaN as well and fails here
+      pass = pass && (fabs(eta[j] + yb) < etamax);
     }
+    pass = pass && (pt2_min > ptmin2);
     // Delta R > R: either Delta eta^2 >= R^2, or cos(Delta phi) < cos(phi0)
-    // with phi0 = sqrt(R^2 - Delta eta^2) <= R; cos(phi0) from its Taylor
+    // with phi0 = sqrt(R^2 - Delta eta^2) <= R.  For Delta eta^2 >= R^2 the
+    // series below is at least 1 and the scalar product never exceeds
+    // pT_i pT_j, so one comparison covers both cases.  cos(phi0) from its Taylor
     // series in z = phi0^2: in FP64 terms to z^6 (remainder below 1e-16 for
     // R <= 0.4), in FP32 to z^3 (for R <= 0.4 the z^4 term is below 1.6e-8,
     // a third of an ulp of the cosine).
@@ -385,7 +392,7 @@ struct WJetsF {
         c = fma(c, -z, T(1.0 / 2.0));
         c = fma(c, -z, T(1));
         const T dot = p[i][1] * p[j][1] + p[i][2] * p[j][2];
-        pass = pass && ((z <= T(0)) || (dot < c * pt[i] * pt[j]));
+        pass = pass && (dot < c * pt[i] * pt[j]);
       }
     if (!pass) return false;
 
