@@ -34,9 +34,14 @@ def cycles(m):
 
 
 def cycle_sum_flops(m):
-    """Flops of the subset dynamic programme over paths from object 0: each
-    (set S, end v) with |S| >= 2 costs one multiply and |S|-2 fmas; closing
-    the full paths costs one multiply, m-2 fmas and the final halving."""
+    """Flops of the colour-ordered sum over cyclic orders.  Six objects use
+    the meet-in-the-middle form: per object z opposite object 0, six two-step
+    arcs (multiply, fma, multiply) and three fmas.  Other sizes use the
+    subset dynamic programme over paths from object 0: each (set S, end v)
+    with |S| >= 2 costs one multiply and |S|-2 fmas; closing the full paths
+    costs one multiply, m-2 fmas and the final halving."""
+    if m == 6:
+        return 5 * (6 * 4 + 3 * 2)
     K = m - 1
     f = 0
     for mask in range(1, 1 << K):

@@ -92,10 +92,15 @@ __device__ __forceinline__ void sample_words(uint32_t s, uint32_t it, uint32_t k
 // The helpers return the offset scaled by 2^24 (an integer below 2^24, exact
 // in FP32), to be multiplied by a width stored times kWidthScale.
 // ---------------------------------------------------------------------------
+// (2m+1) N as m (2N) + N: one 24-bit multiply-add (m < 2^23, 2N <= 512, and
+// the result stays below 2^32).
+__device__ __forceinline__ uint32_t odd_times(uint32_t word, uint32_t n) {
+  return __umul24(word >> 9, 2u * n) + n;
+}
+
 template <typename T>
 __device__ __forceinline__ void bin_plain(uint32_t word, uint32_t nbins, int& j, T& off) {
-  // (2m+1) < 2^24 and nbins <= 256: the 24-bit multiply is exact
-  const uint32_t P = __umul24(((word >> 9) << 1) | 1u, nbins);
+  const uint32_t P = odd_times(word, nbins);
   j = static_cast<int>(P >> 24);
   off = static_cast<T>(static_cast<int>(P & 0xFFFFFFu));
 }
@@ -103,7 +108,7 @@ __device__ __forceinline__ void bin_plain(uint32_t word, uint32_t nbins, int& j,
 template <typename T>
 __device__ __forceinline__ void bin_strat_div(uint32_t word, uint32_t ca, uint32_t per_cube, int& j, T& off) {
   // ng divides nbins; per_cube = nbins / ng
-  const uint32_t P = __umul24(((word >> 9) << 1) | 1u, per_cube);
+  const uint32_t P = odd_times(word, per_cube);
   j = static_cast<int>(ca * per_cube + (P >> 24));
   off = static_cast<T>(static_cast<int>(P & 0xFFFFFFu));
 }

@@ -71,6 +71,31 @@ __device__ __forceinline__ T cycle_sum(const T (&y)[M][M]) {
   return T(0.5) * total;
 }
 
+// Six objects, meet in the middle.  Every cycle through object 0 has one
+// object z opposite 0, and its two arcs are paths 0 -> z through two objects
+// each.  With A(z, {x, w}) = y_xw (y_0x y_wz + y_0w y_xz), the sum over both
+// such paths, the cycle sum is the sum over z and over the three ways to
+// split the other four objects into two pairs {T, T'} of A(z, T) A(z, T').
+// Each undirected cycle appears once (the split is unordered): 105
+// operations instead of the 165 of the subset recursion.
+template <typename T>
+__device__ __forceinline__ T cycle_sum6(const T (&y)[6][6]) {
+  T total = T(0);
+#pragma unroll
+  for (int z = 1; z <= 5; ++z) {
+    int o[4];
+    int n = 0;
+#pragma unroll
+    for (int v = 1; v <= 5; ++v)
+      if (v != z) o[n++] = v;
+    auto arc = [&](int x, int w) { return y[x][w] * fma(y[0][x], y[w][z], y[0][w] * y[x][z]); };
+    total = fma(arc(o[0], o[1]), arc(o[2], o[3]), total);
+    total = fma(arc(o[0], o[2]), arc(o[1], o[3]), total);
+    total = fma(arc(o[0], o[3]), arc(o[1], o[2]), total);
+  }
+  return total;
+}
+
 // ---------------------------------------------------------------------------
 // Mass step of RAMBO on diet: the fraction t = M_i^2 / M_{i-1}^2 has CDF
 // F(t) = (k+1) t^k - k t^(k+1), k = n - i.  The inversion F(t) = r works on
@@ -436,7 +461,12 @@ struct WJetsF {
       for (int j = i + 1; j < NP; ++j, ++k) y[2 + i][2 + j] = y[2 + j][2 + i] = st.y[k];
 #pragma unroll
     for (int i = 0; i < MC; ++i) y[i][i] = T(0);
-    const T ptsum = cycle_sum<MC, T>(y);
+    T ptsum;
+    if constexpr (MC == 6) {
+      ptsum = cycle_sum6<T>(y);
+    } else {
+      ptsum = cycle_sum<MC, T>(y);
+    }
     // ---- Breit-Wigner in m_enu^2 = M_{n-1}^2 (e nu are the last pair)
     const T dm = st.m2 - Mv2;
     const T invD = vrcp(fma(dm, dm, M2G2));
