@@ -6,8 +6,13 @@ and running combination, and (in the grid-optimisation phase) the grid
 refinement.  `value` is integrand evaluations per second over the timed
 steps (fail-cut samples count as evaluations, as NCALL does in the paper).
 
-Prints ONE JSON line.  See the design doc for the flop census, the roofline peak
-and how the CPU baseline sample is chosen.
+Prints ONE JSON line.  `roofline` sets the forward kernel's census flops
+(paper_1010_2107_amd/census.py) per launch, timed with HIP events on the
+launch stream, against the published FP32 peak and against the FMA and LDS
+atomic rates that probe kernels measure on the chip; `traffic` comes from
+the committed hardware-counter summary when it was taken on the current
+kernel sources.  `cpu_baseline` times the FP64 oracle on a bounded sample of
+the same workload on the host.
 """
 from __future__ import annotations
 
