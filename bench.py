@@ -44,10 +44,9 @@ def source_sha1():
     return h.hexdigest()
 
 
-def measured_traffic(workload_name):
-    """HBM bytes per launch of the forward sample kernel from the committed
-    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy
-    calibration), or None when the summary is missing or was taken on other
+def counter_summary(workload_name):
+    """Key/value lines of the committed hardware-counter summary of the
+    forward sample kernel, or None when it is missing or was taken on other
     kernel sources."""
     p = os.path.join(ROOT, "profiles", f"pmc_sample_kernel_{workload_name}.txt")
     if not os.path.exists(p):
@@ -57,10 +56,25 @@ def measured_traffic(workload_name):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source-sha1") != source_sha1():
-        return None
+    return kv if kv.get("source-sha1") == source_sha1() else None
+
+
+def measured_traffic(workload_name):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy
+    calibration) from the counter summary, or None."""
+    kv = counter_summary(workload_name)
     try:
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv["traffic_bytes_per_launch"]) if kv else None
+    except (KeyError, ValueError):
+        return None
+
+
+def measured_valu(workload_name):
+    """VALU wave instructions per launch (SQ_INSTS_VALU) from the counter
+    summary, or None."""
+    kv = counter_summary(workload_name)
+    try:
+        return float(kv["SQ_INSTS_VALU"]) if kv else None
     except (KeyError, ValueError):
         return None
 
@@ -433,6 +447,19 @@ def main(argv=None):
     L.call("vmc_probe_fp32_fma", 8192, 4096, ctypes.byref(fma), stream)
     roof["fp32_fma_probe"] = {"peak_tflops": fma.value / 1e12, "frac": achieved / (fma.value / 1e12),
                               "note": "8 independent FP32 FMA chains per lane, packed FP32 off"}
+    # instruction-mix ceiling: the launch cannot be shorter than its VALU
+    # instructions at the probe's issue rate (one wave FMA = 2 x 64 flops)
+    valu = measured_valu(w.name)
+    if valu:
+        issue = fma.value / 128.0
+        t_min = valu / issue
+        roof["instruction_mix"] = {
+            "valu_per_launch": valu, "min_launch_ms": t_min * 1e3, "issue_frac": t_min / (avg_ms / 1e3),
+            "ceiling_tflops": flops * n_eff / t_min / 1e12,
+            "note": "SQ_INSTS_VALU from the committed counter summary over the same 20 iterations; "
+                    "issue rate from the FMA probe"}
+    else:
+        roof["instruction_mix"] = None
     peak = ctypes.c_double()
     L.call("vmc_probe_lds_atomics", 2048, 4096, ctypes.byref(peak), stream)
     lds_achieved = 2 * w.dim * n_eff / (avg_ms / 1e3)
