@@ -303,7 +303,11 @@ int launch_sample(vmc_grid_t g, const Plan& P, int kind, hipStream_t stream) {
   if (!fn) return fail(VMC_E_INTEGRAND, "integrand has no parameters to differentiate");
   size_t lds = P.lds;
   if (kind & KIND_FWD) lds += sizeof(double) * 2 * static_cast<size_t>(P.d) * P.A.nbins;
-  if (!P.strat) lds += static_cast<size_t>(P.ks->queue_bytes);
+  if (!P.strat) {
+    lds += static_cast<size_t>(P.ks->queue_bytes);
+  } else if (!(kind & KIND_ADJ)) {
+    lds += static_cast<size_t>(P.ks->strat_queue_bytes);
+  }
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return fail(VMC_E_NBINS, "dim x nbins needs %zu bytes of LDS per block: %s", lds,

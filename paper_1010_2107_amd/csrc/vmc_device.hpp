@@ -206,6 +206,14 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// LDS maximum of a positive double: non-negative doubles order like their
+// bit patterns read as unsigned 64-bit integers.  The slot starts at +0.
+__device__ __forceinline__ void lds_max_pos(double* p, double v) {
+  __hip_atomic_fetch_max(reinterpret_cast<unsigned long long*>(p),
+                         static_cast<unsigned long long>(__double_as_longlong(v)), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 __device__ __forceinline__ void global_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 
 // Sum NV per-thread values over the block and add the totals to dst[idx[i]]

@@ -152,6 +152,17 @@ template <class F>
 constexpr int queue_bytes() {
   return StagedTraits<F>::value ? (kBlock / kWave) * kQueueCap * queue_words<F>() * 4 : 0;
 }
+// The stratified forward kernels queue the owner lane with each entry and
+// keep, per wave, three slots per lane (sum w, sum w^2, largest w of the
+// lane's cube chunk) that other lanes add into.
+template <class F>
+constexpr int strat_queue_words() {
+  return queue_words<F>() + 1;
+}
+template <class F>
+constexpr int strat_queue_bytes() {
+  return StagedTraits<F>::value ? (kBlock / kWave) * (3 * kWave * 8 + kQueueCap * strat_queue_words<F>() * 4) : 0;
+}
 
 // LDS layout: grid table first (16-byte entries for FP64), then the histogram
 // [2][d][N] (adjacent bins 8 bytes apart, so a wave's random bins spread
@@ -431,6 +442,9 @@ __global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
 // k samples s = c + t M between them.  After the cube's samples the chunk
 // sums are combined with lane shuffles and the first lane adds the cube's
 // k S2_c - S1_c^2 (and its gradient analogue) to the variance sums.
+// Forward passes of integrands that split at the cuts queue the samples that
+// pass, as the plain kernel does; a queued sample's weight returns to the
+// chunk it belongs to through that lane's LDS slots.
 // ---------------------------------------------------------------------------
 template <class F, int KIND>
 __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
@@ -478,27 +492,123 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
       double cg1[NG + 1], cg2[NG + 1];
 #pragma unroll
       for (int q = 0; q < NG; ++q) cg1[q] = cg2[q] = 0.0;
-      for (uint32_t t = t0; t < t1; ++t) {
-        const uint32_t s = c + t * A.M;
-        uint32_t w[D];
-        sample_words<D>(s, A.it, A.kid, A.key, w);
-        int j[D];
-        T x[D], jac;
-        make_point<T, D, true>(A, tab, w, cc, j, x, jac);
-        T g[F::NGRAD + 1];
-        const T fv = fn.template eval<GRAD>(x, g);
-        accumulate<F, KIND>(A, hist, j, fv, jac, g, acc, cnt);
-        if (FWD) {
-          const double wd = static_cast<double>(fv * jac);
-          c1 += wd;
-          c2 += wd * wd;
-          if (CMAX) cm = fmax(cm, wd);  // a NaN weight never becomes the maximum
-        }
+      if constexpr (StagedTraits<F>::value && !GRAD) {
+        // Stage 1 for every sample of the chunk (the loop runs to the
+        // longest chunk of the wave), stage 2 on full waves of queued samples.
+        constexpr int NQ = strat_queue_words<F>();
+        constexpr int NS = StagedTraits<F>::words;
+        constexpr int NPK = (D + 3) / 4;
+        using State = typename F::State;
+        const int lane = threadIdx.x & (kWave - 1);
+        double* slot = hist + 2 * D * A.nbins + (threadIdx.x / kWave) * 3 * kWave;  // [3][64]
+        float* q = reinterpret_cast<float*>(hist + 2 * D * A.nbins + (kBlock / kWave) * 3 * kWave) +
+                   (threadIdx.x / kWave) * NQ * kQueueCap;
+        uint32_t* qj = reinterpret_cast<uint32_t*>(q + (NS + 1) * kQueueCap);
+        uint32_t* qo = qj + NPK * kQueueCap;  // owner lane
+        slot[lane] = 0.0;
+        slot[kWave + lane] = 0.0;
+        slot[2 * kWave + lane] = 0.0;
+        __builtin_amdgcn_wave_barrier();
+        auto push = [&](int e, const State& st, T jc, const uint32_t (&pk)[NPK]) {
+          F::store_state(st, q, kQueueCap, e);
+          q[NS * kQueueCap + e] = static_cast<float>(jc);
 #pragma unroll
-        for (int q = 0; q < NG; ++q) {
-          const double gq = static_cast<double>(g[q] * jac);
-          cg1[q] += gq;
-          cg2[q] += gq * gq;
+          for (int v = 0; v < NPK; ++v) qj[v * kQueueCap + e] = pk[v];
+          qo[e] = static_cast<uint32_t>(lane);
+        };
+        auto pop = [&](int e, State& st, T& jc, uint32_t (&pk)[NPK], int& owner) {
+          st = F::load_state(q, kQueueCap, e);
+          jc = static_cast<T>(q[NS * kQueueCap + e]);
+#pragma unroll
+          for (int v = 0; v < NPK; ++v) pk[v] = qj[v * kQueueCap + e];
+          owner = static_cast<int>(qo[e]);
+        };
+        auto run = [&](const State& st, T jc, const uint32_t (&pk)[NPK], int owner) {
+          int j[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) j[a] = static_cast<int>((pk[a / 4] >> (8 * (a % 4))) & 0xFFu);
+          T g[F::NGRAD + 1];
+          const T fv = fn.template stage2<false>(st, g);
+          accumulate<F, KIND>(A, hist, j, fv, jc, g, acc, cnt);
+          const double wd = static_cast<double>(fv * jc);
+          if (owner == lane) {
+            c1 += wd;
+            c2 += wd * wd;
+            if (CMAX) cm = fmax(cm, wd);  // a NaN weight never becomes the maximum
+          } else {
+            lds_add(&slot[owner], wd);
+            lds_add(&slot[kWave + owner], wd * wd);
+            if (CMAX && wd > 0.0) lds_max_pos(&slot[2 * kWave + owner], wd);
+          }
+        };
+        const uint32_t nt = static_cast<uint32_t>((static_cast<uint64_t>(A.k) + G - 1) >> A.log2G);
+        int qn = 0;  // entries waiting (wave-uniform)
+        for (uint32_t i = 0; i < nt; ++i) {
+          const uint32_t t = t0 + i;
+          bool pass = false;
+          State st;
+          uint32_t pk[NPK] = {};
+          T jc = T(0);
+          if (t < t1) {  // t1 = 0 for inactive units
+            uint32_t w[D];
+            sample_words<D>(c + t * A.M, A.it, A.kid, A.key, w);
+            T x[D];
+            int j[D];
+            make_point<T, D, true>(A, tab, w, cc, j, x, jc);
+#pragma unroll
+            for (int a = 0; a < D; ++a) pk[a / 4] |= static_cast<uint32_t>(j[a]) << (8 * (a % 4));
+            pass = fn.stage1(x, st);
+            cnt[1] += pass ? 0u : 1u;  // f = 0 outside the cuts
+          }
+          const uint64_t m = __ballot(pass);
+          const int np = static_cast<int>(__popcll(m));
+          if (qn + np >= kWave) {
+            int owner = lane;
+            if (!pass) pop(qn - 1 - static_cast<int>(__popcll(~m & __lanemask_lt())), st, jc, pk, owner);
+            run(st, jc, pk, owner);
+            qn -= kWave - np;
+          } else {
+            if (pass) push(qn + static_cast<int>(__popcll(m & __lanemask_lt())), st, jc, pk);
+            qn += np;
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+        if (lane < qn) {
+          State st;
+          T jc;
+          uint32_t pk[NPK];
+          int owner;
+          pop(lane, st, jc, pk, owner);
+          run(st, jc, pk, owner);
+        }
+        __builtin_amdgcn_wave_barrier();
+        c1 += slot[lane];
+        c2 += slot[kWave + lane];
+        if (CMAX) cm = fmax(cm, slot[2 * kWave + lane]);
+        __builtin_amdgcn_wave_barrier();
+      } else {
+        for (uint32_t t = t0; t < t1; ++t) {
+          const uint32_t s = c + t * A.M;
+          uint32_t w[D];
+          sample_words<D>(s, A.it, A.kid, A.key, w);
+          int j[D];
+          T x[D], jac;
+          make_point<T, D, true>(A, tab, w, cc, j, x, jac);
+          T g[F::NGRAD + 1];
+          const T fv = fn.template eval<GRAD>(x, g);
+          accumulate<F, KIND>(A, hist, j, fv, jac, g, acc, cnt);
+          if (FWD) {
+            const double wd = static_cast<double>(fv * jac);
+            c1 += wd;
+            c2 += wd * wd;
+            if (CMAX) cm = fmax(cm, wd);  // a NaN weight never becomes the maximum
+          }
+#pragma unroll
+          for (int q = 0; q < NG; ++q) {
+            const double gq = static_cast<double>(g[q] * jac);
+            cg1[q] += gq;
+            cg2[q] += gq * gq;
+          }
         }
       }
       for (uint32_t off = 1; off < G; off <<= 1) {
@@ -585,7 +695,22 @@ __global__ __launch_bounds__(kBlock) void k_dump(const DumpArgs P) {
     make_point<T, D, false>(A, tab, w, cc, j, x, jac);
   }
   T g[F::NGRAD + 1];
-  const T fv = fn.template eval<false>(x, g);
+  T fv;
+  if constexpr (StagedTraits<F>::value) {
+    // The sample kernels hand the stage-1 state to stage 2 through LDS or a
+    // register merge, where no multiply-add can fuse across the boundary;
+    // the state goes through an opaque copy here as well, so the dump gives
+    // the weights those kernels add up, bit for bit.
+    typename F::State st;
+    const bool pass = fn.stage1(x, st);
+    float sw[StagedTraits<F>::words];
+    F::store_state(st, sw, 1, 0);
+#pragma unroll
+    for (int i = 0; i < StagedTraits<F>::words; ++i) asm volatile("" : "+v"(sw[i]));
+    fv = pass ? fn.template stage2<false>(F::load_state(sw, 1, 0), g) : T(0);
+  } else {
+    fv = fn.template eval<false>(x, g);
+  }
   if (P.words) {
 #pragma unroll
     for (int a = 0; a < D; ++a) P.words[i * D + a] = w[a];

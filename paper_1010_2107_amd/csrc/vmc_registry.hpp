@@ -15,7 +15,8 @@ struct KernelSet {
   const void* strat[8];  // and KIND_FWD | KIND_CMAX
   const void* dump;
   const void* spring;
-  int queue_bytes;  // LDS of the plain kernels' stage-2 queue (0: unstaged)
+  int queue_bytes;        // LDS of the plain kernels' stage-2 queue (0: unstaged)
+  int strat_queue_bytes;  // LDS of the stratified forward kernels' queue and slots (0: unstaged)
   int ngrad;
   int ntheta;
   int tab_entry_bytes;
@@ -36,6 +37,7 @@ KernelSet make_kernel_set() {
   s.dump = reinterpret_cast<const void*>(&k_dump<F>);
   s.spring = reinterpret_cast<const void*>(&k_spring<F>);
   s.queue_bytes = queue_bytes<F>();
+  s.strat_queue_bytes = strat_queue_bytes<F>();
   s.ngrad = F::NGRAD;
   s.ntheta = F::NTHETA;
   s.tab_entry_bytes = static_cast<int>(sizeof(typename TabEntry<typename F::T>::type));

@@ -1,0 +1,115 @@
+"""Forward passes of the integrands that split at the cuts (W + partons,
+helicity amplitudes) in FP32, whose kernels queue the samples that pass and
+run stage 2 on full waves.  In stratified (BASES) mode each queued weight
+returns to its cube chunk through an LDS slot of the lane that drew it.
+Checks:
+
+- Replay: the oracle accumulates the GPU's own FP32 weights (dumped per
+  sample) in FP64 (Kawabata's per-cube variance over ng^d cubes), and the
+  cube maxima are the maxima of those weights (at least 0).  The dump runs
+  the same stages in another kernel, where the compiler may fuse a
+  different set of multiply-adds: for the one-gluon helicity integrand the
+  dumped weights differ from the accumulated ones by a few ulps (replayed
+  sums 2e-9 apart), for the others not at all (1e-14).  Bounds: S1, S2, I
+  at 1e-7, the variance and the bins at 1e-6, each cube maximum at 1e-6
+  relative, the zero-weight count exactly.  A weight added to the wrong
+  cube would move that cube's terms by O(1).
+- End to end against the oracle's FP64 integrand: S1 at 1e-5, S2 at 2e-5,
+  V at 1e-4, bin plane 0 at 5e-5 and plane 1 at 1e-4.  The bins get the
+  looser bound because at these sizes a bin can hold a few heavy events
+  whose FP32 weights carry 1e-5 relative errors (events near the cuts,
+  where the invariants cancel).  A few cube maxima may differ where an FP32
+  cut decision flips at a threshold.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1010_2107_amd import WHEL, WJETS, Grid
+from paper_1010_2107_amd import workloads as W
+from tests.gpu_util import announce, normwise, rel, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ("wjets_d10_ng2", WJETS, 10, W.WJETS_THETA, 2, 400),
+    ("wjets_d16_ng2", WJETS, 16, W.WJETS_THETA, 2, 6),
+    ("whel_d8_ng2", WHEL, 8, W.WHEL_THETA, 2, 400),
+    ("whel_d11_ng2", WHEL, 11, W.WHEL_THETA, 2, 60),
+]
+
+
+@pytest.mark.parametrize("case", [("wjets_d10", WJETS, 10, W.WJETS_THETA), ("wjets_d16", WJETS, 16, W.WJETS_THETA),
+                                  ("whel_d8", WHEL, 8, W.WHEL_THETA), ("whel_d11", WHEL, 11, W.WHEL_THETA)],
+                         ids=lambda c: c[0])
+def test_fp32_plain_staged_replay(case):
+    """The plain kernel's stage-2 queue: the oracle's FP64 accumulation of the
+    dumped FP32 weights gives the GPU's sums (bounds as above)."""
+    require_gpu()
+    name, iid, d, th = case
+    announce(f"plain staged replay {name}")
+    N, ncall = 64, 300_007
+    e = O.integrate(iid, d, N, th, 40_000, 2, 32).edges
+    g = Grid(d, N)
+    g.set_edges(e)
+    g.iterate(iid, th, ncall, 4321, 3)
+    r = g.result()
+    dump = g.dump(iid, th, ncall, 4321, 3, 0, ncall)
+    rep = O.iterate(iid, e, th, ncall, 4321, 3, w_in=dump["w"])
+    print(f"{name}: replay S1 {rel(r['S1'], rep['S1']):.1e} bins {normwise(g.bins.cpu().numpy(), rep['bins']):.1e}")
+    for key in ("S1", "S2", "I"):
+        assert rel(r[key], rep[key]) <= 1e-7, key
+    assert normwise(g.bins.cpu().numpy(), rep["bins"]) <= 1e-6
+    assert r["n_zero"] == int(np.count_nonzero(dump["w"] == 0))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_fp32_stratified_matches_oracle(case):
+    require_gpu()
+    name, iid, d, th, ng, k = case
+    announce(f"stratified fp32 {name}")
+    N = 64
+    M = ng ** d
+    ncall = M * k + 7
+    e = O.integrate(iid, d, N, th, 40_000, 2, 31).edges
+    g = Grid(d, N)
+    g.stratify(ng)
+    g.set_edges(e)
+    buf = torch.zeros(M, dtype=torch.float64, device="cuda")
+    g.bind_cube_max(buf)
+    g.iterate(iid, th, ncall, 1234, 5)
+    r = g.result()
+    assert r["n_eff"] == M * k and r["nonfinite"] == 0
+    bins = g.bins.cpu().numpy()
+    got_max = buf.cpu().numpy()
+
+    # replay: the oracle's FP64 accumulation of the GPU's FP32 weights
+    dump = g.dump(iid, th, ncall, 1234, 5, 0, r["n_eff"])
+    rep = O.iterate(iid, e, th, ncall, 1234, 5, ng=ng, w_in=dump["w"])
+    print(f"{name}: replay S1 {rel(r['S1'], rep['S1']):.1e} var {rel(r['var'], rep['var']):.1e} "
+          f"bins {normwise(bins, rep['bins']):.1e}")
+    for key in ("S1", "S2", "I"):
+        assert rel(r[key], rep[key]) <= 1e-7, key
+    assert rel(r["var"], rep["var"]) <= 1e-6
+    assert normwise(bins, rep["bins"]) <= 1e-6
+    assert r["n_zero"] == int(np.count_nonzero(dump["w"] == 0))
+    w = dump["w"].astype(np.float64)
+    want_max = np.zeros(M)
+    np.maximum.at(want_max, np.arange(w.size) % M, w)
+    assert np.all(np.abs(got_max - want_max) <= 1e-6 * want_max)
+
+    # end to end against the FP64 integrand
+    ref = O.iterate(iid, e, th, ncall, 1234, 5, ng=ng)
+    cm = np.zeros(M)
+    O.cube_max(iid, e, th, ncall, 1234, 5, ng, cm)
+    print(f"{name}: S1 {rel(r['S1'], ref['S1']):.1e} S2 {rel(r['S2'], ref['S2']):.1e} V {rel(r['V'], ref['V']):.1e} "
+          f"bins {normwise(bins[0], ref['bins'][0]):.1e} {normwise(bins[1], ref['bins'][1]):.1e}")
+    assert rel(r["S1"], ref["S1"]) <= 1e-5
+    assert rel(r["S2"], ref["S2"]) <= 2e-5
+    assert rel(r["V"], ref["V"]) <= 1e-4
+    assert normwise(bins[0], ref["bins"][0]) <= 5e-5
+    assert normwise(bins[1], ref["bins"][1]) <= 1e-4
+    close = np.abs(got_max - cm) <= 1e-4 * np.abs(cm) + 1e-300
+    print(f"{name}: cube maxima within 1e-4 of the oracle's: {close.mean():.4f}")
+    assert close.mean() >= 0.99
