@@ -173,8 +173,8 @@ int vmc_set_schedule(vmc_grid_t g, int block_samples, int chunks_per_cube) {
     return fail(VMC_E_SCHEDULE, "block_samples %d: need 0 or a multiple of %d in [%d, 2^24]", block_samples,
                 kBlock, kBlock);
   if (chunks_per_cube != 0 &&
-      (chunks_per_cube < 1 || chunks_per_cube > 64 || (chunks_per_cube & (chunks_per_cube - 1))))
-    return fail(VMC_E_SCHEDULE, "chunks_per_cube %d: need 0 or a power of two in [1, 64]", chunks_per_cube);
+      (chunks_per_cube < 1 || chunks_per_cube > kBlock || (chunks_per_cube & (chunks_per_cube - 1))))
+    return fail(VMC_E_SCHEDULE, "chunks_per_cube %d: need 0 or a power of two in [1, %d]", chunks_per_cube, kBlock);
   g->block_items = block_samples;
   g->chunks = chunks_per_cube;
   return VMC_OK;
@@ -245,12 +245,12 @@ int plan_launch(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
     A.ncall = k * M;
     P.n_eff = static_cast<double>(k * M);
     // built-in lanes per cube: enough cube units (M G) to give every SIMD
-    // of the chip a few waves (2^18 lanes), at most one wave per cube and
-    // at most k lanes per cube
+    // of the chip a few waves (2^18 lanes), at most one block per cube and
+    // at most k/2 lanes per cube
     uint32_t G = static_cast<uint32_t>(g->chunks);
     if (!G) {
       G = 1;
-      while (G < 64 && 2 * static_cast<uint64_t>(G) <= k && M * G < (1ull << 18)) G <<= 1;
+      while (G < kBlock && 2 * static_cast<uint64_t>(G) <= k && M * G < (1ull << 18)) G <<= 1;
     }
     uint32_t lg = 0;
     while ((1u << lg) < G) ++lg;

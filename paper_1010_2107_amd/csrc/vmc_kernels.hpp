@@ -438,10 +438,11 @@ __global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
 
 // ---------------------------------------------------------------------------
 // Stratified (BASES) sampling.  A unit is (cube c, chunk g); the 2^log2G
-// chunks of one cube sit on adjacent lanes of one wave and split the cube's
-// k samples s = c + t M between them.  After the cube's samples the chunk
-// sums are combined with lane shuffles and the first lane adds the cube's
-// k S2_c - S1_c^2 (and its gradient analogue) to the variance sums.
+// chunks of one cube sit on adjacent lanes (up to 64 in a wave, up to 256
+// across the waves of a block) and split the cube's k samples s = c + t M
+// between them.  After the cube's samples the chunk sums are combined with
+// lane shuffles (and through LDS across waves) and the first lane adds the
+// cube's k S2_c - S1_c^2 (and its gradient analogue) to the variance sums.
 // Forward passes of integrands that split at the cuts queue the samples that
 // pass, as the plain kernel does; a queued sample's weight returns to the
 // chunk it belongs to through that lane's LDS slots.
@@ -611,7 +612,8 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
           }
         }
       }
-      for (uint32_t off = 1; off < G; off <<= 1) {
+      const uint32_t Gw = G < kWave ? G : static_cast<uint32_t>(kWave);  // chunks of a cube in one wave
+      for (uint32_t off = 1; off < Gw; off <<= 1) {
         if (FWD) {
           c1 += __shfl_xor(c1, off, kWave);
           c2 += __shfl_xor(c2, off, kWave);
@@ -622,6 +624,38 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
           cg1[q] += __shfl_xor(cg1[q], off, kWave);
           cg2[q] += __shfl_xor(cg2[q], off, kWave);
         }
+      }
+      if (G > static_cast<uint32_t>(kWave)) {
+        // a cube spans G/64 waves of the block (units come in runs of
+        // kBlock, a multiple of G): their partial sums meet in LDS
+        __shared__ double xw[kBlock / kWave][3 + 2 * NG];
+        const int wv = threadIdx.x / kWave;
+        const bool head = (threadIdx.x & (kWave - 1)) == 0;
+        if (head) {
+          xw[wv][0] = c1;
+          xw[wv][1] = c2;
+          xw[wv][2] = cm;
+#pragma unroll
+          for (int q = 0; q < NG; ++q) {
+            xw[wv][3 + 2 * q] = cg1[q];
+            xw[wv][4 + 2 * q] = cg2[q];
+          }
+        }
+        __syncthreads();
+        const int per = static_cast<int>(G / kWave);
+        if (head && wv % per == 0) {
+          for (int o = 1; o < per; ++o) {
+            c1 += xw[wv + o][0];
+            c2 += xw[wv + o][1];
+            cm = fmax(cm, xw[wv + o][2]);
+#pragma unroll
+            for (int q = 0; q < NG; ++q) {
+              cg1[q] += xw[wv + o][3 + 2 * q];
+              cg2[q] += xw[wv + o][4 + 2 * q];
+            }
+          }
+        }
+        __syncthreads();
       }
       if (active && gidx == 0) {
         if (FWD) acc[kA0 + 2 * NG] += kd * c2 - c1 * c1;

@@ -42,6 +42,10 @@ def test_host_side_errors_without_gpu():
         with pytest.raises(V.VmcError) as e:
             L.call("vmc_set_schedule", h, 0, 3)
         assert e.value.name == "VMC_E_SCHEDULE"
+        with pytest.raises(V.VmcError) as e:
+            L.call("vmc_set_schedule", h, 0, 512)
+        assert e.value.name == "VMC_E_SCHEDULE"
+        L.call("vmc_set_schedule", h, 0, 256)
         L.call("vmc_set_schedule", h, 512, 8)
         with pytest.raises(V.VmcError) as e:
             L.call("bases_stratify", h, 1 << 11)  # (2^11)^4 = 2^44 cubes

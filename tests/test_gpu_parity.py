@@ -169,7 +169,8 @@ def test_schedule_invariance():
     announce("schedule invariance")
     d, N, theta = 8, 128, (1 / 3, 2 / 3, 0.1)
     for ng, ncall, scheds in ((1, 777_777, [(0, 0), (256, 0), (4096, 0), (65536, 0)]),
-                              (4, 4**8 * 20 + 3, [(0, 0), (256, 1), (1024, 4), (2048, 16), (256, 64)])):
+                              (4, 4**8 * 20 + 3, [(0, 0), (256, 1), (1024, 4), (2048, 16), (256, 64),
+                                                  (512, 128), (256, 256)])):
         out = []
         for bs, ch in scheds:
             g = Grid(d, N)
