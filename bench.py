@@ -29,18 +29,23 @@ sys.path.insert(0, ROOT)
 
 def source_sha1():
     """Hash of the sources the sample kernels are built from (device headers,
-    the integrand instantiations and the launch code), identifying the
-    kernel build that a hardware-counter summary was taken on."""
+    the integrand instantiations and the launch code) with comments and
+    blank space removed, identifying the kernel build that a
+    hardware-counter summary was taken on."""
     import glob
     import hashlib
+    import re
     h = hashlib.sha1()
     csrc = os.path.join(ROOT, "paper_1010_2107_amd", "csrc")
     files = sorted(glob.glob(os.path.join(csrc, "*.hpp")) + glob.glob(os.path.join(csrc, "inst_*.hip")) +
                    [os.path.join(csrc, "vmc_capi.hip")])
     for f in files:
-        with open(f, "rb") as fh:
-            h.update(os.path.basename(f).encode())
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(os.path.basename(f).encode())
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

@@ -60,7 +60,7 @@ enum : int { KIND_FWD = 1, KIND_ADJ = 2, KIND_FUSED = 3, KIND_CMAX = 4 };
 constexpr int kA0 = 4;
 
 struct SampleArgs {
-  const float* table32;  // [d][N][2] (lo, width), FP32
+  const float* table32;  // [d][N][2] (lo, width x 2^-24), FP32
   const double* edges;   // [d][N+1], FP64
   double* bins;          // [2][d][N] published bin sums
   double* stripes;       // kStripes copies of stripe_len doubles (block partial sums)
