@@ -240,6 +240,8 @@ int plan_launch(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
                   (unsigned long long)k, (unsigned long long)M);
     A.ng = static_cast<uint32_t>(g->ng);
     A.per_cube = (g->N % g->ng == 0) ? static_cast<uint32_t>(g->N / g->ng) : 0u;
+    A.ngdiv = make_divu32(A.ng);
+    A.ng_inv = 1.0 / static_cast<double>(A.ng);
     A.M = static_cast<uint32_t>(M);
     A.k = static_cast<uint32_t>(k);
     A.ncall = k * M;
@@ -609,6 +611,8 @@ int spring_generate(vmc_grid_t g, int integrand, const double* theta, int ntheta
   A.nbins = static_cast<uint32_t>(g->N);
   A.ng = static_cast<uint32_t>(g->ng);
   A.per_cube = (g->N % g->ng == 0) ? static_cast<uint32_t>(g->N / g->ng) : 0u;
+  A.ngdiv = make_divu32(A.ng);
+  A.ng_inv = 1.0 / static_cast<double>(A.ng);
   A.M = static_cast<uint32_t>(S.M);
   SP.prefix = prefix;
   SP.guide = guide;

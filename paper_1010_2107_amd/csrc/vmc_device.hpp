@@ -92,6 +92,45 @@ __device__ __forceinline__ void sample_words(uint32_t s, uint32_t it, uint32_t k
 // The helpers return the offset scaled by 2^24 (an integer below 2^24, exact
 // in FP32), to be multiplied by a width stored times kWidthScale.
 // ---------------------------------------------------------------------------
+// Division of 32-bit words by a launch-constant divisor d >= 2 through a
+// precomputed multiplier (Granlund and Montgomery, "Division by invariant
+// integers using multiplication", PLDI 1994, Sec. 4): with l = ceil(log2 d)
+// and m = floor(2^32 (2^l - d) / d) + 1, t = mulhi(m, n) gives
+// n / d = (t + ((n - t) >> 1)) >> (l - 1) exactly for every 32-bit n.
+// m = 1 exactly when d is a power of two.
+struct DivU32 {
+  uint32_t d, m, sh;  // divisor, multiplier, l - 1
+};
+inline DivU32 make_divu32(uint32_t d) {  // d >= 2
+  uint32_t l = 0;
+  while ((uint64_t{1} << l) < d) ++l;
+  const uint64_t m = ((uint64_t{1} << 32) * ((uint64_t{1} << l) - d)) / d + 1;
+  return DivU32{d, static_cast<uint32_t>(m), l - 1};
+}
+
+__device__ __forceinline__ uint32_t divu32(uint32_t n, const DivU32& v) {
+  const uint32_t t = __umulhi(n, v.m);
+  return (t + ((n - t) >> 1)) >> v.sh;
+}
+
+// The D base-d digits of c (least significant first).  The branch on the
+// divisor's form is uniform across the launch.
+template <int D>
+__device__ __forceinline__ void digits(uint32_t c, const DivU32& v, uint32_t (&cc)[D]) {
+  if (v.m == 1) {
+    const uint32_t mask = v.d - 1, l = v.sh + 1;
+#pragma unroll
+    for (int a = 0; a < D; ++a) cc[a] = (c >> (l * a)) & mask;
+  } else {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const uint32_t q = divu32(c, v);
+      cc[a] = c - q * v.d;
+      c = q;
+    }
+  }
+}
+
 // (2m+1) N as m (2N) + N: one 24-bit multiply-add (m < 2^23, 2N <= 512, and
 // the result stays below 2^32).
 __device__ __forceinline__ uint32_t odd_times(uint32_t word, uint32_t n) {
@@ -109,18 +148,26 @@ template <typename T>
 __device__ __forceinline__ void bin_strat_div(uint32_t word, uint32_t ca, uint32_t per_cube, int& j, T& off) {
   // ng divides nbins; per_cube = nbins / ng
   const uint32_t P = odd_times(word, per_cube);
-  j = static_cast<int>(ca * per_cube + (P >> 24));
+  j = static_cast<int>(__umul24(ca, per_cube) + (P >> 24));
   off = static_cast<T>(static_cast<int>(P & 0xFFFFFFu));
 }
 
+// ng does not divide nbins: the point lies at (ca + (2m+1) 2^-24) / ng on
+// the axis, and Q = (ca 2^24 + 2m + 1) N is that position times N ng 2^24.
+// The bin is floor(Q / (ng 2^24)) = floor(floor(Q / 2^24) / ng), where
+// floor(Q / 2^24) < ng N fits 32 bits, and the offset, in units of 2^-24 of
+// the bin, is (Q mod ng 2^24) / ng, formed from its two parts with the
+// reciprocal of ng.
 template <typename T>
-__device__ __forceinline__ void bin_strat_gen(uint32_t word, uint32_t ca, uint32_t ng, uint32_t nbins,
-                                              int& j, T& off) {
+__device__ __forceinline__ void bin_strat_gen(uint32_t word, uint32_t ca, const DivU32& ng, uint32_t nbins,
+                                              T inv_ng, int& j, T& off) {
   const uint64_t Q = ((static_cast<uint64_t>(ca) << 24) + ((word >> 9) * 2u + 1u)) * nbins;
-  const uint64_t Dn = static_cast<uint64_t>(ng) << 24;
-  const uint64_t q = Q / Dn;
+  const uint32_t hi = static_cast<uint32_t>(Q >> 24);
+  const uint32_t q = divu32(hi, ng);
   j = static_cast<int>(q);
-  off = static_cast<T>(static_cast<double>(Q - q * Dn) / static_cast<double>(Dn) * 16777216.0);
+  const T rhi = static_cast<T>(hi - q * ng.d);                             // < ng
+  const T rlo = static_cast<T>(static_cast<int>(static_cast<uint32_t>(Q) & 0xFFFFFFu));  // < 2^24
+  off = fma(rhi, inv_ng * static_cast<T>(16777216.0), rlo * inv_ng);
 }
 
 // A grid's table holds per bin the lower edge and the width times

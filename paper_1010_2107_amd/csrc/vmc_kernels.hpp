@@ -72,6 +72,8 @@ struct SampleArgs {
   uint32_t nbins;
   uint32_t ng;        // <= 1: plain
   uint32_t per_cube;  // nbins / ng when ng divides nbins, else 0
+  DivU32 ngdiv;       // division by ng (stratified)
+  double ng_inv;      // 1 / ng (stratified)
   uint32_t M;         // cubes
   uint32_t k;         // samples per cube
   uint32_t log2G;     // lanes per cube = 1 << log2G
@@ -199,7 +201,7 @@ __device__ __forceinline__ void make_point(const SampleArgs& A, const typename T
     } else if (A.per_cube) {
       bin_strat_div<T>(w[a], cc[a], A.per_cube, j[a], off);
     } else {
-      bin_strat_gen<T>(w[a], cc[a], A.ng, A.nbins, j[a], off);
+      bin_strat_gen<T>(w[a], cc[a], A.ngdiv, A.nbins, static_cast<T>(A.ng_inv), j[a], off);
     }
     const auto e = tab[a * N + j[a]];
     x[a] = fma(off, e.y, e.x);
@@ -477,15 +479,7 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
       const uint32_t c = static_cast<uint32_t>(u >> A.log2G);
       const uint32_t gidx = static_cast<uint32_t>(u) & (G - 1);
       uint32_t cc[D];
-      {
-        uint32_t r = c;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          const uint32_t q = r / A.ng;
-          cc[a] = r - q * A.ng;
-          r = q;
-        }
-      }
+      digits<D>(c, A.ngdiv, cc);
       const uint32_t t0 = active ? static_cast<uint32_t>((static_cast<uint64_t>(gidx) * A.k) >> A.log2G) : 0u;
       const uint32_t t1 =
           active ? static_cast<uint32_t>((static_cast<uint64_t>(gidx + 1) * A.k) >> A.log2G) : 0u;

@@ -129,16 +129,9 @@ __global__ __launch_bounds__(kBlock) void k_spring(const SpringArgs P) {
       const uint32_t c = lo;
       const double g = static_cast<double>(P.prefix[c + 1] - P.prefix[c]) * unit;
       uint32_t cc[D], wp[D];
-      {
-        uint32_t rem = c;
+      digits<D>(c, A.ngdiv, cc);
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-          const uint32_t q = rem / A.ng;
-          cc[a] = rem - q * A.ng;
-          rem = q;
-          wp[a] = w[a];
-        }
-      }
+      for (int a = 0; a < D; ++a) wp[a] = w[a];
       int j[D];
       T jac;
       make_point<T, D, true>(A, tab, wp, cc, j, x, jac);

@@ -117,13 +117,14 @@ def test_setup_matches_oracle(shape):
     assert guide[K] == O.spring_pick(q_ref, TWO64 - 1)
 
 
-@pytest.fixture(scope="module")
-def gauss2():
+@pytest.fixture(scope="module", params=[8, 5], ids=["ng8", "ng5"])
+def gauss2(request):
     """A BASES grid and cube maxima from the oracle for the 2-D per-axis
-    Gaussian product (ng = 8, 64 cubes)."""
+    Gaussian product (ng = 8: 64 cubes, each 4 bins wide; ng = 5: 25 cubes
+    that do not split the 32 bins evenly)."""
     th = (0.35, 0.6, 0.15)
-    ng = 8
-    run = O.integrate(W.GAUSS_AXES, 2, 32, th, 8 * 8 * 1000, 4, 21, ng=ng, itmx2=2, cube_max_phase2=True)
+    ng = request.param
+    run = O.integrate(W.GAUSS_AXES, 2, 32, th, ng * ng * 1000, 4, 21, ng=ng, itmx2=2, cube_max_phase2=True)
     q, unit = O.spring_envelope(run.wmax)
     return dict(th=th, ng=ng, edges=run.edges, wmax=run.wmax, q=q, unit=unit)
 
@@ -211,7 +212,8 @@ def test_error_paths(gauss2):
     with pytest.raises(VmcError) as ei:
         sp.generate(W.GAUSS_AXES, G["th"], 1, 0, 0, 100, ev)  # no set-up yet
     assert ei.value.name == "VMC_E_SPRING"
-    for bad in (np.zeros(64), np.full(64, np.nan), np.r_[np.ones(63), np.inf]):
+    M = G["ng"] ** 2
+    for bad in (np.zeros(M), np.full(M, np.nan), np.r_[np.ones(M - 1), np.inf]):
         with pytest.raises(VmcError) as ei:
             sp.setup(torch.from_numpy(bad).cuda())
         assert ei.value.name == "VMC_E_SPRING"
