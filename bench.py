@@ -131,9 +131,41 @@ def cpu_baseline(w, edges, budget_s=15.0):
     t0 = time.perf_counter()
     r = O.iterate(w.integrand, edges, w.theta, ncall, w.seed, 1000, ng=w.ng)
     dt = time.perf_counter() - t0
-    return dict(value=r["n_eff"] / dt, unit="evals/s", cores=1, kind="oracle",
-                sample=f"one oracle iteration of {r['n_eff']} samples of this workload on the GPU-adapted grid "
-                       f"({dt:.1f} s, 1 thread, {platform.processor() or platform.machine()})")
+    out = dict(value=r["n_eff"] / dt, unit="evals/s", cores=1, kind="oracle",
+               sample=f"one oracle iteration of {r['n_eff']} samples of this workload on the GPU-adapted grid "
+                      f"({dt:.1f} s, 1 thread, {platform.processor() or platform.machine()})")
+    if w.ng <= 1:
+        out["all_cores"] = cpu_baseline_all_cores(w, edges, min(w.ncall, 8 * ncall))
+    return out
+
+
+def cpu_baseline_all_cores(w, edges, ncall):
+    """The same oracle with one iteration split into contiguous sample
+    ranges over a pool of worker processes, one per host core available to
+    this process (at most 16).  It runs in a child process that never
+    touches the GPU (oracle/cpu_rate.py)."""
+    import subprocess
+    import tempfile
+
+    import numpy as np
+    try:
+        nproc = max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        nproc = max(1, min(16, os.cpu_count() or 1))
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "edges.npy")
+        np.save(path, np.asarray(edges, dtype=np.float64))
+        cfg = dict(integrand=int(w.integrand), edges=path, theta=list(w.theta), ncall=int(ncall), seed=int(w.seed),
+                   it=1001, nproc=nproc)
+        try:
+            p = subprocess.run([sys.executable, "-m", "oracle.cpu_rate", json.dumps(cfg)], cwd=ROOT,
+                               capture_output=True, text=True, timeout=300)
+            res = json.loads(p.stdout.strip().splitlines()[-1])
+        except Exception as e:  # reported, not fatal: the GPU figures stand on their own
+            return dict(error=f"{type(e).__name__}: {e}")
+    return dict(value=res["samples"] / res["seconds"], unit="evals/s", cores=res["procs"], kind="oracle",
+                sample=f"one oracle iteration of {res['samples']} samples split over {res['procs']} worker "
+                       f"processes ({res['seconds']:.1f} s)")
 
 
 def measure_workload(grid, w, steps, warmup):

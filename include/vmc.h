@@ -215,11 +215,14 @@ int vmc_dump_samples(vmc_grid_t g, int integrand, const double *theta, int nthet
 /* Launch shape of the sample kernels: one tile per thread block.
  * block_samples: samples (plain) or cube units (stratified) per tile, a
  * multiple of 256 in [256, 2^24], or 0 for the built-in choice (plain: at
- * least 1024 tiles of at most 8192 samples; stratified: about 512 tiles);
+ * least 1024 tiles of at most 8192 samples; stratified: 256 units, one
+ * per thread, or up to 1024 when a unit holds few samples, toward 4096
+ * samples per tile, but at least about 512 tiles);
  * chunks_per_cube: lanes that share one cube in stratified mode, a power of
  * two in [1, 256] (up to 64 share a wave, more span the waves of a block),
  * or 0 for the built-in choice (the smallest power of two with ng^dim x
- * lanes >= 2^18, at most 256 and at most k/2).  Errors: VMC_E_SCHEDULE. */
+ * lanes >= 2^19 for the W + partons and helicity integrands, 2^18 for the
+ * others, at most 256 and at most k/2).  Errors: VMC_E_SCHEDULE. */
 int vmc_set_schedule(vmc_grid_t g, int block_samples, int chunks_per_cube);
 
 /* Kernel timing with HIP events recorded on the launch stream around every

@@ -246,13 +246,15 @@ int plan_launch(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
     A.k = static_cast<uint32_t>(k);
     A.ncall = k * M;
     P.n_eff = static_cast<double>(k * M);
-    // built-in lanes per cube: enough cube units (M G) to give every SIMD
-    // of the chip a few waves (2^18 lanes), at most one block per cube and
-    // at most k/2 lanes per cube
+    // built-in lanes per cube: enough cube units (M G, one per lane) for a
+    // few rounds of resident blocks (2^19 lanes for the integrands that queue
+    // stage 2, whose longer samples amortise the per-unit combine; 2^18 for
+    // the others), at most one block per cube and at most k/2 lanes per cube
     uint32_t G = static_cast<uint32_t>(g->chunks);
     if (!G) {
+      const uint64_t lanes = P.ks->strat_queue_bytes ? (1ull << 19) : (1ull << 18);
       G = 1;
-      while (G < kBlock && 2 * static_cast<uint64_t>(G) <= k && M * G < (1ull << 18)) G <<= 1;
+      while (G < kBlock && 2 * static_cast<uint64_t>(G) <= k && M * G < lanes) G <<= 1;
     }
     uint32_t lg = 0;
     while ((1u << lg) < G) ++lg;
@@ -319,8 +321,17 @@ int launch_sample(vmc_grid_t g, const Plan& P, int kind, hipStream_t stream) {
   if (!A.block_items) {
     // built-in: one tile per block; plain: at least 1024 blocks, at most
     // 8192 samples per block (short blocks even out the cut-dependent cost
-    // and the tail of the last wave); stratified: about 512 blocks
-    uint64_t b = P.strat ? (P.items + 511) / 512 : (P.items + 1023) / 1024;
+    // and the tail of the last wave); stratified: one cube unit per lane,
+    // or two or four when units are short, toward 4096 samples per block
+    // (the table load and the bin flush are per block), but at least about
+    // 512 blocks
+    uint64_t b = (P.items + 1023) / 1024;
+    if (P.strat) {
+      const double per_unit = static_cast<double>(A.k) / static_cast<double>(1u << A.log2G);
+      uint64_t r = 1;
+      while (r < 4 && 2.0 * static_cast<double>(r * kBlock) * per_unit <= 4096.0) r <<= 1;
+      b = std::min<uint64_t>(r * kBlock, (P.items + 511) / 512);
+    }
     b = ((b + kBlock - 1) / kBlock) * kBlock;
     b = std::max<uint64_t>(b, kBlock);
     if (!P.strat) b = std::min<uint64_t>(b, 8192);

@@ -193,15 +193,27 @@ __device__ __forceinline__ void make_point(const SampleArgs& A, const typename T
   const T Nk2 = Nk * Nk;  // <= 2^64 for N <= 256: exact
   jac = T(1);
   T wprev = T(0);
+  // stratified: the bins of all axes first, with the (launch-uniform) choice
+  // of bin map taken once, so that the table reads below form one
+  // straight-line run
+  T offs[D];
+  if constexpr (STRAT) {
+    if (A.per_cube) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) bin_strat_div<T>(w[a], cc[a], A.per_cube, j[a], offs[a]);
+    } else {
+      const T inv = static_cast<T>(A.ng_inv);
+#pragma unroll
+      for (int a = 0; a < D; ++a) bin_strat_gen<T>(w[a], cc[a], A.ngdiv, A.nbins, inv, j[a], offs[a]);
+    }
+  }
 #pragma unroll
   for (int a = 0; a < D; ++a) {
     T off;
-    if (!STRAT) {
+    if constexpr (!STRAT) {
       bin_plain<T>(w[a], A.nbins, j[a], off);
-    } else if (A.per_cube) {
-      bin_strat_div<T>(w[a], cc[a], A.per_cube, j[a], off);
     } else {
-      bin_strat_gen<T>(w[a], cc[a], A.ngdiv, A.nbins, static_cast<T>(A.ng_inv), j[a], off);
+      off = offs[a];
     }
     const auto e = tab[a * N + j[a]];
     x[a] = fma(off, e.y, e.x);
@@ -449,8 +461,16 @@ __global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
 // pass, as the plain kernel does; a queued sample's weight returns to the
 // chunk it belongs to through that lane's LDS slots.
 // ---------------------------------------------------------------------------
+// The queued forward passes ask for at least 3 waves per SIMD, the
+// occupancy of the plain kernel, which bounds their registers at 168.
 template <class F, int KIND>
-__global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
+constexpr int strat_min_waves() {
+  return (StagedTraits<F>::value && !(KIND & KIND_ADJ)) ? 3 : 1;
+}
+
+template <class F, int KIND>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(strat_min_waves<F, KIND>())))
+void k_strat(const SampleArgs A) {
   using T = typename F::T;
   constexpr int D = F::D;
   constexpr bool FWD = KIND & KIND_FWD, GRAD = KIND & KIND_ADJ, CMAX = KIND & KIND_CMAX;
@@ -478,8 +498,37 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
       const bool active = u < u1;
       const uint32_t c = static_cast<uint32_t>(u >> A.log2G);
       const uint32_t gidx = static_cast<uint32_t>(u) & (G - 1);
-      uint32_t cc[D];
-      digits<D>(c, A.ngdiv, cc);
+      // The unit's cube coordinates.  From dim 4 up (ng < 256, as
+      // ng^dim <= 2^31) they are packed four to a word and taken apart again
+      // for every sample behind an opaque copy: held whole, they and the
+      // per-axis values derived from them would stay live across the
+      // sample loop in dim registers each.
+      constexpr bool PACK = D >= 4;
+      uint32_t ccp[PACK ? (D + 3) / 4 : D];
+      {
+        uint32_t cc[D];
+        digits<D>(c, A.ngdiv, cc);
+        if constexpr (PACK) {
+#pragma unroll
+          for (int v = 0; v < (D + 3) / 4; ++v) ccp[v] = 0u;
+#pragma unroll
+          for (int a = 0; a < D; ++a) ccp[a / 4] |= cc[a] << (8 * (a % 4));
+        } else {
+#pragma unroll
+          for (int a = 0; a < D; ++a) ccp[a] = cc[a];
+        }
+      }
+      auto coords = [&](uint32_t (&cc)[D]) {
+        if constexpr (PACK) {
+#pragma unroll
+          for (int v = 0; v < (D + 3) / 4; ++v) asm volatile("" : "+v"(ccp[v]));
+#pragma unroll
+          for (int a = 0; a < D; ++a) cc[a] = (ccp[a / 4] >> (8 * (a % 4))) & 0xFFu;
+        } else {
+#pragma unroll
+          for (int a = 0; a < D; ++a) cc[a] = ccp[a];
+        }
+      };
       const uint32_t t0 = active ? static_cast<uint32_t>((static_cast<uint64_t>(gidx) * A.k) >> A.log2G) : 0u;
       const uint32_t t1 =
           active ? static_cast<uint32_t>((static_cast<uint64_t>(gidx + 1) * A.k) >> A.log2G) : 0u;
@@ -549,6 +598,8 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
             sample_words<D>(c + t * A.M, A.it, A.kid, A.key, w);
             T x[D];
             int j[D];
+            uint32_t cc[D];
+            coords(cc);
             make_point<T, D, true>(A, tab, w, cc, j, x, jc);
 #pragma unroll
             for (int a = 0; a < D; ++a) pk[a / 4] |= static_cast<uint32_t>(j[a]) << (8 * (a % 4));
@@ -588,6 +639,8 @@ __global__ __launch_bounds__(kBlock) void k_strat(const SampleArgs A) {
           sample_words<D>(s, A.it, A.kid, A.key, w);
           int j[D];
           T x[D], jac;
+          uint32_t cc[D];
+          coords(cc);
           make_point<T, D, true>(A, tab, w, cc, j, x, jac);
           T g[F::NGRAD + 1];
           const T fv = fn.template eval<GRAD>(x, g);

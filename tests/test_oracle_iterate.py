@@ -10,6 +10,7 @@ grid, the stratified variance 1/(12 M^3 k) of f = x, exact zero variance for
 a constant, and the known integrals of the Gaussian configurations.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -201,3 +202,24 @@ def test_sharded_iteration_equals_single_iteration():
         assert abs(got[key] - ref[key]) <= 1e-12 * abs(ref[key])
     assert np.allclose(got["bins"], ref["bins"], rtol=1e-12, atol=0)
     assert got["n_eff"] == ref["n_eff"]
+
+
+def test_cpu_rate_child_runs_the_same_iteration(tmp_path):
+    """The all-core CPU-baseline timer (a child process with a worker pool)
+    evaluates the same iteration as the single-thread oracle."""
+    import json
+    import subprocess
+    import sys
+    rng = np.random.default_rng(13)
+    e = _grid(rng, 4, 16)
+    th = [0.4, 0.6, 0.15]
+    np.save(tmp_path / "edges.npy", e)
+    cfg = dict(integrand=O.DGAUSS, edges=str(tmp_path / "edges.npy"), theta=th, ncall=50_001, seed=5, it=2, nproc=2)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, "-m", "oracle.cpu_rate", json.dumps(cfg)], cwd=root, capture_output=True,
+                       text=True, timeout=120, check=True)
+    got = json.loads(p.stdout.strip().splitlines()[-1])
+    ref = O.iterate(O.DGAUSS, e, th, 50_001, 5, 2)
+    assert got["samples"] == 50_001 and got["procs"] == 2 and got["seconds"] > 0
+    assert abs(got["I"] - ref["I"]) <= 1e-12 * abs(ref["I"])
+    assert abs(got["var"] - ref["var"]) <= 1e-10 * abs(ref["var"])
