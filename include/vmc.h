@@ -221,8 +221,9 @@ int vmc_dump_samples(vmc_grid_t g, int integrand, const double *theta, int nthet
  * chunks_per_cube: lanes that share one cube in stratified mode, a power of
  * two in [1, 256] (up to 64 share a wave, more span the waves of a block),
  * or 0 for the built-in choice (the smallest power of two with ng^dim x
- * lanes >= 2^19 for the W + partons and helicity integrands, 2^18 for the
- * others, at most 256 and at most k/2).  Errors: VMC_E_SCHEDULE. */
+ * lanes >= 2^18, at most 256 and at most k; then, for the W + partons and
+ * helicity integrands, doubled toward 2^19 while each lane keeps at least
+ * 8 samples).  Errors: VMC_E_SCHEDULE. */
 int vmc_set_schedule(vmc_grid_t g, int block_samples, int chunks_per_cube);
 
 /* Kernel timing with HIP events recorded on the launch stream around every

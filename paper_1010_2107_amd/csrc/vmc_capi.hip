@@ -246,15 +246,16 @@ int plan_launch(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
     A.k = static_cast<uint32_t>(k);
     A.ncall = k * M;
     P.n_eff = static_cast<double>(k * M);
-    // built-in lanes per cube: enough cube units (M G, one per lane) for a
-    // few rounds of resident blocks (2^19 lanes for the integrands that queue
-    // stage 2, whose longer samples amortise the per-unit combine; 2^18 for
-    // the others), at most one block per cube and at most k/2 lanes per cube
+    // built-in lanes per cube (at most one block per cube): first enough
+    // cube units (M G, one per lane) to fill the chip (2^18), down to one or
+    // two samples per unit; then, for the integrands that queue stage 2,
+    // up to 2^19 units while units keep at least 8 samples
     uint32_t G = static_cast<uint32_t>(g->chunks);
     if (!G) {
-      const uint64_t lanes = P.ks->strat_queue_bytes ? (1ull << 19) : (1ull << 18);
       G = 1;
-      while (G < kBlock && 2 * static_cast<uint64_t>(G) <= k && M * G < lanes) G <<= 1;
+      while (G < kBlock && 2 * static_cast<uint64_t>(G) <= k && M * G < (1ull << 18)) G <<= 1;
+      if (P.ks->strat_queue_bytes)
+        while (G < kBlock && 16 * static_cast<uint64_t>(G) <= k && M * G < (1ull << 19)) G <<= 1;
     }
     uint32_t lg = 0;
     while ((1u << lg) < G) ++lg;
