@@ -113,3 +113,37 @@ def test_fp32_stratified_matches_oracle(case):
     close = np.abs(got_max - cm) <= 1e-4 * np.abs(cm) + 1e-300
     print(f"{name}: cube maxima within 1e-4 of the oracle's: {close.mean():.4f}")
     assert close.mean() >= 0.99
+
+
+@pytest.mark.parametrize("case", [("wjets_d10_ng2", WJETS, 10, W.WJETS_THETA, 2, 4096),
+                                  ("whel_d8_ng2", WHEL, 8, W.WHEL_THETA, 2, 3000),
+                                  ("wjets_d10_ng3", WJETS, 10, W.WJETS_THETA, 3, 70)],
+                         ids=lambda c: c[0])
+def test_queued_schedule_invariance(case):
+    """The queued stratified kernel under the built-in schedule and under
+    explicit ones (one lane per cube up to 256 lanes spanning the block's
+    waves, one to four units per lane): every sample's FP32 weight is the
+    same, so the FP64 sums agree to summation order (1e-12) and the
+    zero-weight count exactly."""
+    require_gpu()
+    name, iid, d, th, ng, k = case
+    announce(f"queued schedule invariance {name}")
+    M = ng ** d
+    ncall = M * k + 5
+    e = O.integrate(iid, d, 64, th, 40_000, 2, 33).edges
+    out = []
+    for bs, ch in ((0, 0), (256, 1), (1024, 8), (256, 64), (512, 128), (256, 256)):
+        if ch > k:
+            continue
+        g = Grid(d, 64)
+        g.stratify(ng)
+        g.set_edges(e)
+        g.set_schedule(bs, ch)
+        g.iterate(iid, th, ncall, 99, 2)
+        out.append(((bs, ch), g.result(), g.bins.cpu().numpy()))
+    _, r0, b0 = out[0]
+    for sched, r, b in out[1:]:
+        for key in ("S1", "S2", "V", "I"):
+            assert rel(r[key], r0[key]) <= 1e-12, (sched, key)
+        assert r["n_zero"] == r0["n_zero"], sched
+        assert normwise(b, b0) <= 1e-12, sched
