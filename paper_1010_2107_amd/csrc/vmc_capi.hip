@@ -242,6 +242,7 @@ int plan_launch(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
     A.per_cube = (g->N % g->ng == 0) ? static_cast<uint32_t>(g->N / g->ng) : 0u;
     A.ngdiv = make_divu32(A.ng);
     A.ng_inv = 1.0 / static_cast<double>(A.ng);
+    A.ng_wide = static_cast<uint64_t>(A.ng) * A.nbins >= (1ull << 32) ? 1u : 0u;
     A.M = static_cast<uint32_t>(M);
     A.k = static_cast<uint32_t>(k);
     A.ncall = k * M;
@@ -625,6 +626,7 @@ int spring_generate(vmc_grid_t g, int integrand, const double* theta, int ntheta
   A.per_cube = (g->N % g->ng == 0) ? static_cast<uint32_t>(g->N / g->ng) : 0u;
   A.ngdiv = make_divu32(A.ng);
   A.ng_inv = 1.0 / static_cast<double>(A.ng);
+  A.ng_wide = static_cast<uint64_t>(A.ng) * A.nbins >= (1ull << 32) ? 1u : 0u;
   A.M = static_cast<uint32_t>(S.M);
   SP.prefix = prefix;
   SP.guide = guide;

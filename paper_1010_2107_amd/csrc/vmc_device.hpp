@@ -155,9 +155,9 @@ __device__ __forceinline__ void bin_strat_div(uint32_t word, uint32_t ca, uint32
 // ng does not divide nbins: the point lies at (ca + (2m+1) 2^-24) / ng on
 // the axis, and Q = (ca 2^24 + 2m + 1) N is that position times N ng 2^24.
 // The bin is floor(Q / (ng 2^24)) = floor(floor(Q / 2^24) / ng), where
-// floor(Q / 2^24) < ng N fits 32 bits, and the offset, in units of 2^-24 of
-// the bin, is (Q mod ng 2^24) / ng, formed from its two parts with the
-// reciprocal of ng.
+// floor(Q / 2^24) < ng N fits 32 bits when ng N < 2^32, and the offset, in
+// units of 2^-24 of the bin, is (Q mod ng 2^24) / ng, formed from its two
+// parts with the reciprocal of ng.
 template <typename T>
 __device__ __forceinline__ void bin_strat_gen(uint32_t word, uint32_t ca, const DivU32& ng, uint32_t nbins,
                                               T inv_ng, int& j, T& off) {
@@ -168,6 +168,18 @@ __device__ __forceinline__ void bin_strat_gen(uint32_t word, uint32_t ca, const 
   const T rhi = static_cast<T>(hi - q * ng.d);                             // < ng
   const T rlo = static_cast<T>(static_cast<int>(static_cast<uint32_t>(Q) & 0xFFFFFFu));  // < 2^24
   off = fma(rhi, inv_ng * static_cast<T>(16777216.0), rlo * inv_ng);
+}
+
+// The same map when ng N >= 2^32 (one axis cut into more than 2^32 / N
+// cubes): a 64-bit division and an FP64 quotient for the offset.
+template <typename T>
+__device__ __forceinline__ void bin_strat_wide(uint32_t word, uint32_t ca, uint32_t ng, uint32_t nbins, int& j,
+                                               T& off) {
+  const uint64_t Q = ((static_cast<uint64_t>(ca) << 24) + ((word >> 9) * 2u + 1u)) * nbins;
+  const uint64_t Dn = static_cast<uint64_t>(ng) << 24;
+  const uint64_t q = Q / Dn;
+  j = static_cast<int>(q);
+  off = static_cast<T>(static_cast<double>(Q - q * Dn) / static_cast<double>(ng));
 }
 
 // A grid's table holds per bin the lower edge and the width times

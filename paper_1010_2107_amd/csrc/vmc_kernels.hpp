@@ -74,6 +74,7 @@ struct SampleArgs {
   uint32_t per_cube;  // nbins / ng when ng divides nbins, else 0
   DivU32 ngdiv;       // division by ng (stratified)
   double ng_inv;      // 1 / ng (stratified)
+  uint32_t ng_wide;   // ng nbins >= 2^32 (stratified, ng not dividing nbins)
   uint32_t M;         // cubes
   uint32_t k;         // samples per cube
   uint32_t log2G;     // lanes per cube = 1 << log2G
@@ -201,10 +202,13 @@ __device__ __forceinline__ void make_point(const SampleArgs& A, const typename T
     if (A.per_cube) {
 #pragma unroll
       for (int a = 0; a < D; ++a) bin_strat_div<T>(w[a], cc[a], A.per_cube, j[a], offs[a]);
-    } else {
+    } else if (D > 1 || !A.ng_wide) {
       const T inv = static_cast<T>(A.ng_inv);
 #pragma unroll
       for (int a = 0; a < D; ++a) bin_strat_gen<T>(w[a], cc[a], A.ngdiv, A.nbins, inv, j[a], offs[a]);
+    } else if constexpr (D == 1) {
+      // ng N >= 2^32 needs ng > 2^24, which ng^dim <= 2^31 allows on one axis only
+      bin_strat_wide<T>(w[0], cc[0], A.ng, A.nbins, j[0], offs[0]);
     }
   }
 #pragma unroll

@@ -230,6 +230,29 @@ def test_edge_cases():
     assert g.result()["nonfinite"] == 5000
 
 
+def test_stratified_wide_axis():
+    """One axis cut into about 2^24 cubes at 256 bins (ng does not divide
+    nbins): ng N just below 2^32 takes the 32-bit quotient of the bin map,
+    just above it the 64-bit one.  FP64 instantiation against the oracle;
+    the oracle adds its 3.4e7 terms in order, so S1 gets that sum's bound
+    (n - 1) 2^-53 and the bins 1e-10.  The variance is not compared: with
+    two samples in a cube 2^-24 wide, k S2_c - S1_c^2 = (w1 - w2)^2 cancels
+    to rounding level in either implementation."""
+    announce("stratified wide axis")
+    theta = (0.3, 0.7, 0.12)
+    for ng in (2**24 - 3, 2**24 + 3):
+        ncall = 2 * ng + 1
+        g = Grid(1, 256)
+        g.stratify(ng)
+        g.iterate(W.DGAUSS, theta, ncall, 7, 0, fp64=True)
+        r = g.result()
+        ref = O.iterate(W.DGAUSS, O.uniform_edges(1, 256), theta, ncall, 7, 0, ng=ng)
+        bound = (ncall - 1) * 2.0**-53
+        assert r["n_eff"] == ref["n_eff"] == 2 * ng
+        assert rel(r["S1"], ref["S1"]) <= bound, ng
+        assert normwise(g.bins.cpu().numpy(), ref["bins"]) <= 1e-10, ng
+
+
 def test_error_paths_on_device():
     from paper_1010_2107_amd import VmcError
     announce("error paths")
