@@ -120,5 +120,16 @@ def check(rc: int) -> None:
         raise VmcError(rc, msg)
 
 
+# ctypes wraps an out-of-range Python int silently; the integer arguments
+# are checked against their C type first
+_INT_RANGE = {ctypes.c_int: (-2**31, 2**31), ctypes.c_uint32: (0, 2**32), ctypes.c_int64: (-2**63, 2**63),
+              ctypes.c_uint64: (0, 2**64)}
+
+
 def call(name: str, *args) -> None:
-    check(getattr(lib(), name)(*args))
+    fn = getattr(lib(), name)
+    for i, (a, t) in enumerate(zip(args, fn.argtypes or ())):
+        lim = _INT_RANGE.get(t)
+        if lim is not None and isinstance(a, int) and not lim[0] <= a < lim[1]:
+            raise ValueError(f"{name}: argument {i} = {a} does not fit {t.__name__}")
+    check(fn(*args))

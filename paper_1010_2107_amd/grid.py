@@ -63,7 +63,10 @@ class Grid:
         L.call("vmc_reset", self._h, _stream_ptr(stream))
 
     def stratify(self, ng: int):
-        L.call("bases_stratify", self._h, int(ng))
+        ng = int(ng)
+        if not 0 <= ng < 2**31:  # the C call takes an int
+            raise ValueError(f"ng = {ng} outside [0, 2^31)")
+        L.call("bases_stratify", self._h, ng)
         self.ng = max(int(ng), 1)
 
     def bind_cube_max(self, buf: torch.Tensor | None):

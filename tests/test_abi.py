@@ -84,3 +84,15 @@ def test_batch_create_validation():
         L.call("vmc_iterate_batched", h, 1, 0, 1, 0, None)
     assert e.value.name == "VMC_E_UNBOUND"
     L.call("vmc_batch_destroy", h)
+
+
+def test_integer_arguments_are_range_checked():
+    """ctypes would wrap 2^31 into a negative int (ng = 2^31 would silently
+    mean plain sampling); the binding refuses values that do not fit."""
+    sizes = (ctypes.c_size_t * 4)()
+    with pytest.raises(ValueError):
+        L.call("vmc_workspace_sizes", 2**31, 64, sizes)
+    with pytest.raises(ValueError):
+        L.call("vmc_workspace_sizes", 4, -2**31 - 1, sizes)
+    L.call("vmc_workspace_sizes", 4, 64, sizes)
+    assert sizes[0] == 8 * 4 * 65

@@ -253,6 +253,30 @@ def test_stratified_wide_axis():
         assert normwise(g.bins.cpu().numpy(), ref["bins"]) <= 1e-10, ng
 
 
+def test_maximum_sizes():
+    """The largest call count, ncall = 2^32: plain, and stratified with one
+    axis cut into 2^30 cubes of k = 4 (through the 64-bit bin map; ng is a
+    C int, so 2^31 - 1 is the largest ng the call takes).  A constant
+    integrand makes every sum exact: S1 = c n, zero variance, and in
+    stratified mode each of the 256 bins holds exactly 2^24 samples."""
+    announce("maximum sizes")
+    n = 2**32
+    g = Grid(1, 256)
+    g.iterate(W.CONST, (2.5,), n, 3, 0, fp64=True)
+    r = g.result()
+    b = g.bins.cpu().numpy()
+    assert r["n_eff"] == n and r["S1"] == 2.5 * n and r["var"] == 0.0
+    assert b[0].sum() == 2.5 * n and b[1].sum() == 6.25 * n
+    with pytest.raises(ValueError):
+        g.stratify(2**31)
+    g.stratify(2**30)
+    g.iterate(W.CONST, (2.5,), n, 3, 1, fp64=True)
+    r = g.result()
+    b = g.bins.cpu().numpy()
+    assert r["n_eff"] == n and r["S1"] == 2.5 * n and r["V"] == 0.0 and r["var"] == 0.0
+    assert np.all(b[0] == 2.5 * 2**24) and np.all(b[1] == 6.25 * 2**24)
+
+
 def test_error_paths_on_device():
     from paper_1010_2107_amd import VmcError
     announce("error paths")
