@@ -36,7 +36,8 @@ def test_uniform_range_and_centres():
     assert O.uniform(0x1FF) == O.uniform(0)  # low 9 bits ignored
 
 
-@pytest.mark.parametrize("nbins,ng", [(50, 2), (64, 4), (128, 4), (50, 3), (64, 6), (60, 7)])
+@pytest.mark.parametrize("nbins,ng", [(50, 2), (64, 4), (128, 4), (50, 3), (64, 6), (60, 7), (256, (1 << 24) + 3),
+                                      (256, (1 << 31) - 1)])
 def test_strat_bin_vs_real_definition(nbins, ng):
     rng = np.random.default_rng(1000 * nbins + ng)
     n = 1 << 18
@@ -53,7 +54,8 @@ def test_strat_bin_vs_real_definition(nbins, ng):
         q = (Fraction(int(cc[i])) + Fraction(2 * int(m[i]) + 1, 1 << 24)) * nbins / ng
         jref[i] = q.numerator // q.denominator
     assert np.array_equal(j.astype(np.int64), jref)
-    assert np.all((j >= cc * nbins // ng) & (j <= ((cc + 1) * nbins - 1) // ng))
+    c64 = cc.astype(np.int64)
+    assert np.all((j >= c64 * nbins // ng) & (j <= ((c64 + 1) * nbins - 1) // ng))
     assert np.allclose(delta, yN - jref, atol=1e-12, rtol=0)
 
 
