@@ -258,7 +258,8 @@ def test_maximum_sizes():
     axis cut into 2^30 cubes of k = 4 (through the 64-bit bin map; ng is a
     C int, so 2^31 - 1 is the largest ng the call takes).  A constant
     integrand makes every sum exact: S1 = c n, zero variance, and in
-    stratified mode each of the 256 bins holds exactly 2^24 samples."""
+    stratified mode each of the 256 bins holds exactly 2^24 samples; at
+    ng = 2^31 - 1 each bin's count is bracketed by the cubes inside it."""
     announce("maximum sizes")
     n = 2**32
     g = Grid(1, 256)
@@ -275,6 +276,18 @@ def test_maximum_sizes():
     b = g.bins.cpu().numpy()
     assert r["n_eff"] == n and r["S1"] == 2.5 * n and r["V"] == 0.0 and r["var"] == 0.0
     assert np.all(b[0] == 2.5 * 2**24) and np.all(b[1] == 6.25 * 2**24)
+    # the largest ng the call takes, 2^31 - 1 (not a power of two): a bin
+    # holds both samples of every cube inside it, and up to both samples of
+    # each of the two cubes across its edges
+    M = 2**31 - 1
+    g.stratify(M)
+    g.iterate(W.CONST, (2.5,), 2 * M, 3, 2, fp64=True)
+    r = g.result()
+    b = g.bins.cpu().numpy()
+    assert r["n_eff"] == 2 * M and r["S1"] == 2.5 * 2 * M and r["V"] == 0.0
+    full = np.array([((j + 1) * M) // 256 - (-((-j * M) // 256)) for j in range(256)], dtype=np.float64)
+    cnt = b[0][0] / 2.5
+    assert cnt.sum() == 2 * M and np.all(cnt >= 2 * full) and np.all(cnt <= 2 * full + 4)
 
 
 def test_error_paths_on_device():
