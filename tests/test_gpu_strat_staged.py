@@ -37,6 +37,10 @@ CASES = [
     ("wjets_d16_ng2", WJETS, 16, W.WJETS_THETA, 2, 6),
     ("whel_d8_ng2", WHEL, 8, W.WHEL_THETA, 2, 400),
     ("whel_d11_ng2", WHEL, 11, W.WHEL_THETA, 2, 60),
+    # ng = 3 does not divide the 64 bins: the FP32 bin map with the quotient
+    # and remainder by ng
+    ("wjets_d10_ng3", WJETS, 10, W.WJETS_THETA, 3, 3),
+    ("whel_d8_ng3", WHEL, 8, W.WHEL_THETA, 3, 20),
 ]
 
 
