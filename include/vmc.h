@@ -46,7 +46,9 @@ extern "C" {
 #define VMC_E_INTEGRAND (-5) /* unknown integrand id                            */
 #define VMC_E_PARAMS (-6)    /* wrong ntheta                                    */
 #define VMC_E_STRAT (-7)     /* ng^dim > 2^40                                   */
-#define VMC_E_GRID (-8)      /* edges not strictly increasing from 0 to 1       */
+#define VMC_E_GRID (-8)      /* edges not strictly increasing from 0 to 1, or an */
+                             /* adjoint pass on a grid that moved since its     */
+                             /* forward pass                                    */
 #define VMC_E_HIP (-9)       /* a HIP runtime call or launch failed             */
 #define VMC_E_UNBOUND (-10)  /* device buffers not bound with vmc_bind()        */
 #define VMC_E_SCHEDULE (-11) /* schedule values outside their documented range  */
@@ -184,18 +186,39 @@ int vmc_combine_reset(vmc_grid_t g, void *stream);
  * the same samples as vmc_iterate with the same (seed, it) and the grid
  * unchanged since: accumulates sum J df/dtheta_p and its square (and the
  * per-cube form when stratified), then writes G_p and var G_p into the
- * scalar block at VMC_S_GRAD.  It does not touch the bin sums, S1/S2/V,
- * the estimate or the running combination.  Errors: as vmc_iterate, and
- * VMC_E_INTEGRAND for an integrand without parameters. */
+ * scalar block at VMC_S_GRAD (the first ngrad of the 5-double groups, see
+ * vmc_integrand_info; the groups beyond are left as they were).  It does
+ * not touch the bin sums, S1/S2/V, the estimate or the running
+ * combination.  The grid has not moved since the forward pass it
+ * differentiates: the handle's grid-state version (vmc_grid_version) must
+ * equal the one recorded by the last vmc_iterate or vmc_iterate_fused.
+ * Errors: as vmc_iterate; VMC_E_INTEGRAND for an integrand without
+ * parameters; VMC_E_GRID when no forward pass ran on the present grid
+ * state (refine, set_edges, reset, stratify or bind since). */
 int vmc_iterate_adjoint(vmc_grid_t g, int integrand, const double *theta, int ntheta, int64_t ncall,
                         uint64_t seed, uint32_t it, uint32_t flags, void *stream);
 
 /* Forward and adjoint in one pass over the samples: the results of
  * vmc_iterate (bin sums, estimate, running combination) and of
  * vmc_iterate_adjoint (gradient block) at the cost of one sample pass.
- * Errors: as vmc_iterate_adjoint. */
+ * Records the grid-state version as vmc_iterate does.  Errors: as
+ * vmc_iterate, and VMC_E_INTEGRAND for an integrand without parameters. */
 int vmc_iterate_fused(vmc_grid_t g, int integrand, const double *theta, int ntheta, int64_t ncall,
                       uint64_t seed, uint32_t it, uint32_t flags, void *stream);
+
+/* Grid-state version of the handle: a counter advanced by vmc_bind,
+ * vmc_reset, bases_stratify, vmc_refine and vmc_set_edges, i.e. by every
+ * call that can move the samples of an iteration (paper Sec. 2: the grid is
+ * re-optimised between iterations).  A caller that pairs a forward pass
+ * with a later adjoint pass can record it and compare.
+ * Errors: VMC_E_INVALID (NULL argument). */
+int vmc_grid_version(vmc_grid_t g, uint64_t *version);
+
+/* Parameters of a compiled integrand: *ntheta values in theta, of which
+ * the first *ngrad are differentiated by the adjoint pass (either pointer
+ * may be NULL).  Errors: VMC_E_INTEGRAND, VMC_E_DIM (not compiled for
+ * this dimension and precision). */
+int vmc_integrand_info(int integrand, int dim, uint32_t flags, int *ntheta, int *ngrad);
 
 /* Copy the FP64 edges to / from host memory (synchronous on `stream`).
  * vmc_set_edges validates e[a][0] = 0, e[a][nbins] = 1 and strict increase
@@ -203,14 +226,21 @@ int vmc_iterate_fused(vmc_grid_t g, int integrand, const double *theta, int nthe
 int vmc_get_edges(vmc_grid_t g, double *host_edges, void *stream);
 int vmc_set_edges(vmc_grid_t g, const double *host_edges, void *stream);
 
-/* Debug dump of samples s0 .. s0+count-1 of an iteration (same points as
- * vmc_iterate): words [count][dim] u32, w [count], f [count], jac [count]
- * (device arrays; w, f, jac as float, or double with VMC_FLAG_FP64; any
- * may be NULL).  Errors: as vmc_iterate, VMC_E_INVALID for a range beyond
- * ncall (or k ng^dim when stratified). */
+/* Per-sample dump of samples s0 .. s0+count-1 of an iteration (same points
+ * as vmc_iterate): the Philox words [count][dim] u32, the bin index of
+ * every axis [count][dim] u8 (what the accumulation adds the sample into),
+ * w = f J [count], f [count], J [count], and df/dtheta_p [count][ngrad].
+ * Device arrays; w, f, jac and grad are float, or double with
+ * VMC_FLAG_FP64; any may be NULL.  Used by the tests and by the paper's
+ * split of the work (Sec. 3.2: the GPU evaluates, the host accumulates),
+ * which needs the weights and the bin indices on the host.
+ * Errors: as vmc_iterate; VMC_E_INVALID for a range beyond ncall (or
+ * k ng^dim when stratified); VMC_E_INTEGRAND for grad with an integrand
+ * without parameters. */
 int vmc_dump_samples(vmc_grid_t g, int integrand, const double *theta, int ntheta, int64_t ncall,
                      uint64_t seed, uint32_t it, uint32_t flags, int64_t s0, int64_t count,
-                     uint32_t *words, void *w, void *f, void *jac, void *stream);
+                     uint32_t *words, uint8_t *bins, void *w, void *f, void *jac, void *grad,
+                     void *stream);
 
 /* Launch shape of the sample kernels: one tile per thread block.
  * block_samples: samples (plain) or cube units (stratified) per tile, a
@@ -289,8 +319,10 @@ int vmc_batch_reset(vmc_batch_t b, void *stream);
 
 /* One iteration of every integral in one persistent launch: kind 1
  * forward (bin sums, estimate, running combination), 2 adjoint (gradient
- * block only), 3 both in one pass.  Errors: VMC_E_UNBOUND, VMC_E_INVALID,
- * VMC_E_SCHEDULE, VMC_E_HIP. */
+ * block only), 3 both in one pass.  Kind 2 needs a forward pass (kind 1 or
+ * 3) since the last vmc_batch_bind, vmc_batch_reset or vmc_refine_batched.
+ * Errors: VMC_E_UNBOUND, VMC_E_INVALID, VMC_E_SCHEDULE, VMC_E_GRID (kind 2
+ * without that forward pass), VMC_E_HIP. */
 int vmc_iterate_batched(vmc_batch_t b, uint64_t seed, uint32_t it, int kind, uint32_t flags, void *stream);
 
 /* Refine every axis of every integral (one block per axis), as

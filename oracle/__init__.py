@@ -65,6 +65,7 @@ def lib():
     L.orc_eval_samples.argtypes = [c_int, c_int, c_int, dp, c_int, dp, c_int, c_i64, c_u64,
                                    c_u32, c_u32, c_i64, c_i64, u32p, i32p, dp, dp, dp, dp, dp]
     L.orc_refine.argtypes = [c_int, c_int, dp, dp, c_d, dp]
+    L.orc_set_point32.argtypes = [c_int]
     L.orc_accumulate_range.argtypes = [c_int, c_int, c_int, dp, dp, c_int, c_i64, c_u64, c_u32, c_u32, c_i64,
                                        c_i64, dp, ctypes.c_void_p]
     L.orc_estimate_plain.argtypes = [ctypes.c_void_p, c_i64]
@@ -246,9 +247,32 @@ def uniform_edges(d, nbins):
     return np.tile(np.arange(nbins + 1, dtype=np.float64) / nbins, (d, 1))
 
 
-def iterate(integrand_id, edges, theta, ncall, seed, it, kid=0, ng=1, want_grad=False, w_in=None):
+class point32:
+    """Within this context the integrand sees the point as a single-precision
+    grid map forms it (FP32 lower edge and scaled width per bin, one fused
+    multiply-add with the in-bin offset), everything else staying FP64: a
+    single-precision integrand can then be compared with the oracle on
+    identical inputs."""
+
+    def __init__(self, on=True):
+        self.on = bool(on)
+
+    def __enter__(self):
+        lib().orc_set_point32(int(self.on))
+        return self
+
+    def __exit__(self, *exc):
+        lib().orc_set_point32(0)
+        return False
+
+
+def iterate(integrand_id, edges, theta, ncall, seed, it, kid=0, ng=1, want_grad=False, w_in=None, fp32_point=False):
     """One iteration (steps 2-4): returns dict with S1, S2, V, I, var, n_eff,
-    nonfinite, bins [2][d][N] and (if want_grad) per-parameter gradient sums."""
+    nonfinite, bins [2][d][N] and (if want_grad) per-parameter gradient sums.
+    fp32_point: evaluate at the point an FP32 grid map forms (see point32)."""
+    if fp32_point:
+        with point32():
+            return iterate(integrand_id, edges, theta, ncall, seed, it, kid, ng, want_grad, w_in)
     e = _d(edges)
     d, n1 = e.shape
     N = n1 - 1
@@ -309,7 +333,10 @@ def iterate_sharded(integrand_id, edges, theta, ncall, seed, it, pool, nshards, 
     return out
 
 
-def eval_samples(integrand_id, edges, theta, ncall, seed, it, s0, count, kid=0, ng=1):
+def eval_samples(integrand_id, edges, theta, ncall, seed, it, s0, count, kid=0, ng=1, fp32_point=False):
+    if fp32_point:
+        with point32():
+            return eval_samples(integrand_id, edges, theta, ncall, seed, it, s0, count, kid, ng)
     e = _d(edges)
     d, n1 = e.shape
     th = _d(theta)
@@ -400,7 +427,7 @@ def spring_trials(integrand_id, edges, theta, ng, q, unit, seed, pass_, trial0, 
 # ------------------------------------------------------------ driver
 @dataclass
 class Run:
-    I: list = field(default_factory=list)
+    I: list = field(default_factory=list)      # iterations of the last phase (the combined ones)
     var: list = field(default_factory=list)
     Ibar: float = float("nan")
     sigbar: float = float("nan")
@@ -408,6 +435,9 @@ class Run:
     edges: np.ndarray | None = None
     n_eff: int = 0
     wmax: np.ndarray | None = None
+    I_all: list = field(default_factory=list)  # every iteration, both phases
+    var_all: list = field(default_factory=list)
+    edges_seq: list = field(default_factory=list)  # the grid each iteration sampled on
 
 
 def integrate(integrand_id, d, nbins, theta, ncall, itmx, seed, alpha=1.5, ng=1, acc=0.0,
@@ -426,7 +456,10 @@ def integrate(integrand_id, d, nbins, theta, ncall, itmx, seed, alpha=1.5, ng=1,
     for nit, adapt in phases:
         Is, vs = [], []
         for _ in range(nit):
+            run.edges_seq.append(e.copy())
             r = iterate(integrand_id, e, theta, ncall, seed, it, ng=ng)
+            run.I_all.append(r["I"])
+            run.var_all.append(r["var"])
             if cube_max_phase2 and not adapt:
                 cube_max(integrand_id, e, theta, ncall, seed, it, ng, run.wmax)
             it += 1

@@ -818,6 +818,51 @@ static int check_integrand(int id, int d, int ntheta)
 }
 
 /* ===================================================================== */
+/* The point as a single-precision map forms it (the paper evaluates the   */
+/* integrand in single precision, Sec. 3.2).  The grid is held per bin as  */
+/* the lower edge and the width times 2^-24, each rounded once to FP32     */
+/* from the FP64 edges; the in-bin offset is the integer 2^24 delta (plain */
+/* sampling, or stratification with ng dividing N), otherwise the FP32     */
+/* value of (r_hi 2^24 + r_lo) / ng formed as one fused multiply-add of    */
+/* r_hi with (1/ng) 2^24 and the FP32 product r_lo (1/ng), where r_hi =    */
+/* floor(Q / 2^24) mod ng and r_lo = Q mod 2^24 for the position           */
+/* Q = (c 2^24 + 2m + 1) N; the point is one fused multiply-add of the     */
+/* offset and the scaled width onto the lower edge.  This mode changes     */
+/* only the point handed to the integrand (the Jacobian and all arithmetic */
+/* stay FP64); it lets a single-precision integrand be compared with this  */
+/* one on identical inputs.                                                */
+/* ===================================================================== */
+static int g_point32 = 0;
+
+void orc_set_point32(int on) { g_point32 = on ? 1 : 0; }
+
+static double point32_offset(uint32_t word, int cube_coord, int ng, int nbins)
+{
+    uint64_t m = word >> 9;
+    if (ng <= 1) return (double)(((2 * m + 1) * (uint64_t)nbins) & 0xFFFFFFu);
+    uint64_t Q = ((uint64_t)cube_coord * (uint64_t)(1u << 24) + 2 * m + 1) * (uint64_t)nbins;
+    if (nbins % ng == 0) return (double)(Q % ((uint64_t)ng << 24)) / (double)ng; /* an integer */
+    uint64_t hi = Q >> 24;
+    float r_hi = (float)(hi % (uint64_t)ng);
+    float r_lo = (float)(Q & 0xFFFFFFu);
+    float inv = (float)(1.0 / (double)ng);
+    float lo_part = r_lo * inv;
+    return (double)fmaf(r_hi, inv * 16777216.0f, lo_part);
+}
+
+static void point32_map(int d, int nbins, const double *edges, const int32_t *j, const uint32_t *words,
+                        const int *cc, int ng, double *x)
+{
+    for (int a = 0; a < d; ++a) {
+        const double *e = edges + (size_t)a * (size_t)(nbins + 1);
+        float lo = (float)e[j[a]];
+        float w = (float)((e[j[a] + 1] - e[j[a]]) / TWO24);
+        float off = (float)point32_offset(words[a], cc ? cc[a] : 0, ng, nbins);
+        x[a] = (double)fmaf(off, w, lo);
+    }
+}
+
+/* ===================================================================== */
 /* Steps 2-4 for one iteration.                                           */
 /* ===================================================================== */
 typedef struct {
@@ -834,6 +879,7 @@ static double eval_sample(const problem *pb, uint32_t s, uint32_t *words, int32_
 {
     uint32_t wloc[ORC_MAXD];
     double delta[ORC_MAXD];
+    int cc[ORC_MAXD];
     if (!words) words = wloc;
     orc_sample_words(pb->seed, s, pb->it, pb->kid, pb->d, words);
     if (pb->ng <= 1) {
@@ -846,12 +892,14 @@ static double eval_sample(const problem *pb, uint32_t s, uint32_t *words, int32_
         int64_t c = (int64_t)s % pb->ncubes;
         for (int a = 0; a < pb->d; ++a) {
             int jj;
-            orc_bin_strat(words[a], (int)(c % pb->ng), pb->ng, pb->nbins, &jj, &delta[a]);
+            cc[a] = (int)(c % pb->ng);
+            orc_bin_strat(words[a], cc[a], pb->ng, pb->nbins, &jj, &delta[a]);
             j[a] = jj;
             c /= pb->ng;
         }
     }
     double J = orc_map(pb->d, pb->nbins, pb->edges, j, delta, x);
+    if (g_point32) point32_map(pb->d, pb->nbins, pb->edges, j, words, pb->ng > 1 ? cc : NULL, pb->ng, x);
     double fv = orc_integrand(pb->id, pb->d, x, pb->theta, pb->ntheta, grad);
     if (jac) *jac = J;
     if (f) *f = fv;

@@ -78,6 +78,9 @@ void orc_bin_batch(int64_t n, const uint32_t *words, const int32_t *cube_coord, 
 /* ------------------------------------------------------------ grid map */
 /* x_a = e[a][j_a] + delta_a * (e[a][j_a+1]-e[a][j_a]);  returns J = prod N*width */
 double orc_map(int d, int nbins, const double *edges, const int32_t *j, const double *delta, double *x);
+/* Hand the integrand the point as a single-precision grid map forms it
+ * (on != 0) or the FP64 point (0, the default).  Process-wide setting. */
+void orc_set_point32(int on);
 
 /* ----------------------------------------------------------- integrands */
 int orc_integrand_nparams(int id, int d);   /* theta length, <0 on error   */

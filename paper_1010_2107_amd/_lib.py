@@ -63,7 +63,9 @@ _SIGS = {
     "vmc_get_edges": (_c.c_int, [_vp, _vp, _vp]),
     "vmc_set_edges": (_c.c_int, [_vp, _vp, _vp]),
     "vmc_dump_samples": (_c.c_int, [_vp, _c.c_int, _vp, _c.c_int, _c.c_int64, _c.c_uint64, _c.c_uint32, _c.c_uint32,
-                                    _c.c_int64, _c.c_int64, _vp, _vp, _vp, _vp, _vp]),
+                                    _c.c_int64, _c.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "vmc_grid_version": (_c.c_int, [_vp, _c.POINTER(_c.c_uint64)]),
+    "vmc_integrand_info": (_c.c_int, [_c.c_int, _c.c_int, _c.c_uint32, _c.POINTER(_c.c_int), _c.POINTER(_c.c_int)]),
     "vmc_set_schedule": (_c.c_int, [_vp, _c.c_int, _c.c_int]),
     "vmc_timing": (_c.c_int, [_vp, _c.c_int, _c.POINTER(_c.c_double), _c.POINTER(_c.c_int64)]),
     "vmc_batch_create": (_c.c_int, [_c.c_int, _c.POINTER(_c.c_int), _c.c_int, _c.c_int, _c.POINTER(_c.c_int64),
@@ -112,6 +114,14 @@ def lib():
         fn.argtypes = args
     _lib = L
     return L
+
+
+def integrand_info(integrand: int, dim: int, fp64: bool = False) -> tuple[int, int]:
+    """(ntheta, ngrad) of a compiled integrand: theta takes ntheta values, the
+    adjoint pass differentiates the first ngrad of them."""
+    nt, ng = ctypes.c_int(), ctypes.c_int()
+    call("vmc_integrand_info", int(integrand), int(dim), FLAG_FP64 if fp64 else 0, ctypes.byref(nt), ctypes.byref(ng))
+    return nt.value, ng.value
 
 
 def check(rc: int) -> None:

@@ -57,6 +57,8 @@ def measure(batch, spt, blocks, kind=1, reps=3, seed=99):
     """Median kernel time (ms) of `reps` launches with this schedule."""
     batch.set_schedule(spt, blocks)
     batch.reset()
+    if kind == 2:  # an adjoint pass differentiates the forward pass on the same grids
+        batch.iterate(seed, 0, 1)
     batch.iterate(seed, 0, kind)  # warm-up
     torch.cuda.synchronize()
     batch.timing(True)

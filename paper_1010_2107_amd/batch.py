@@ -28,6 +28,7 @@ class Batch:
         nc = (ctypes.c_int64 * self.n)(*self.ncalls.tolist())
         L.call("vmc_batch_create", self.n, d, self.nbins, L.GAUSS_AXES, nc, ctypes.byref(h))
         self._h = h
+        self._destroy = L.lib().vmc_batch_destroy  # outlives the module globals at exit
         # size the work-list buffer for the finest schedule (one tile per 256 samples)
         L.call("vmc_batch_set_schedule", h, 1, 0)
         self._sizes = self._query()
@@ -56,8 +57,9 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and L._lib is not None:
-            L._lib.vmc_batch_destroy(h)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and destroy is not None:
+            destroy(h)
             self._h = None
 
     def set_schedule(self, samples_per_thread=0, blocks=0):

@@ -304,6 +304,10 @@ struct vmc_batch_s {
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used = 0;
+  // grid-state version (bind, reset, refine) and the one of the last
+  // forward pass: an adjoint-only pass needs the two to agree
+  uint64_t version = 1;
+  uint64_t fwd_version = 0;
   ~vmc_batch_s() {
     for (auto& e : events) {
       hipEventDestroy(e.first);
@@ -465,6 +469,7 @@ int vmc_batch_bind(vmc_batch_t b, double* edges, float* table, double* bins, dou
   b->meta = static_cast<unsigned char*>(meta);
   b->meta_cap = meta_bytes_bound;
   b->dirty = true;
+  ++b->version;
   return VMC_OK;
 }
 
@@ -488,6 +493,7 @@ int vmc_batch_reset(vmc_batch_t b, void* stream) {
   const BatchDesc* d = reinterpret_cast<const BatchDesc*>(b->meta + b->off_desc());
   hipLaunchKernelGGL(k_batch_reset, dim3(b->n), dim3(kBlock), 0, st, d, static_cast<uint32_t>(b->n), b->edges,
                      b->table, b->bins, b->scal, b->N);
+  ++b->version;
   HIP_TRY(hipGetLastError(), "k_batch_reset launch");
   return VMC_OK;
 }
@@ -496,6 +502,8 @@ int vmc_iterate_batched(vmc_batch_t b, uint64_t seed, uint32_t it, int kind, uin
   int rc = need_bound(b);
   if (rc) return rc;
   if (kind < 1 || kind > 3) return fail(VMC_E_INVALID, "kind %d: 1 forward, 2 adjoint, 3 both", kind);
+  if (kind == KIND_ADJ && b->fwd_version != b->version)
+    return fail(VMC_E_GRID, "no forward pass on the grids' present state (reset or refine since)");
   hipStream_t st = static_cast<hipStream_t>(stream);
   rc = upload(b, st);
   if (rc) return rc;
@@ -546,6 +554,7 @@ int vmc_iterate_batched(vmc_batch_t b, uint64_t seed, uint32_t it, int kind, uin
   hipLaunchKernelGGL(k_batch_finalize, dim3((b->n + 63) / 64), dim3(64), 0, st, A.desc, b->scal,
                      static_cast<uint32_t>(b->n), fwd ? 1 : 0, grad ? 1 : 0);
   HIP_TRY(hipGetLastError(), "k_batch_finalize launch");
+  if (fwd) b->fwd_version = b->version;
   return VMC_OK;
 }
 
@@ -560,6 +569,7 @@ int vmc_refine_batched(vmc_batch_t b, double alpha, void* stream) {
   const AxisRef* ax = reinterpret_cast<const AxisRef*>(b->meta + b->off_axes());
   hipLaunchKernelGGL(k_batch_refine, dim3(static_cast<unsigned>(b->axes.size())), dim3(kBlock), 0, st, d, ax, b->edges,
                      b->table, b->bins, b->N, alpha);
+  ++b->version;
   HIP_TRY(hipGetLastError(), "k_batch_refine launch");
   return VMC_OK;
 }

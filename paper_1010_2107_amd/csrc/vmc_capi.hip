@@ -71,6 +71,12 @@ struct vmc_grid_s {
   bool timing = false;  // record events around every sample-kernel launch
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used = 0;
+  // Grid-state version: advanced by every call that can change where the
+  // samples land (bind, reset, stratify, refine, set_edges).  A forward pass
+  // records it; an adjoint pass needs the version of the forward pass it
+  // differentiates.
+  uint64_t version = 1;
+  uint64_t fwd_version = 0;  // 0: no forward pass on this state
   bool bound() const { return edges && table && bins && scal; }
   ~vmc_grid_s() {
     for (auto& e : events) {
@@ -90,7 +96,7 @@ extern "C" {
 
 const char* vmc_last_error(void) { return g_last_error.c_str(); }
 
-int vmc_version(void) { return 100; }
+int vmc_version(void) { return 200; }
 
 int vmc_workspace_sizes(int dim, int nbins, size_t out[4]) {
   if (!out) return fail(VMC_E_INVALID, "out is NULL");
@@ -128,6 +134,7 @@ int vmc_bind(vmc_grid_t g, double* edges, float* table, double* bins, double* sc
   g->bins = bins;
   g->scal = scal;
   g->acc_dirty = true;
+  ++g->version;
   return VMC_OK;
 }
 
@@ -144,6 +151,7 @@ int vmc_reset(vmc_grid_t g, void* stream) {
                      g->bins, static_cast<int>(bins_total(g->d, g->N)), g->scal, g->d, g->N);
   HIP_TRY(hipGetLastError(), "k_reset launch");
   g->acc_dirty = false;
+  ++g->version;
   return VMC_OK;
 }
 
@@ -151,11 +159,13 @@ int bases_stratify(vmc_grid_t g, int ng) {
   if (!g) return fail(VMC_E_INVALID, "grid handle is NULL");
   if (ng <= 1) {
     g->ng = 1;
+    ++g->version;
     return VMC_OK;
   }
   double cubes = std::pow(static_cast<double>(ng), g->d);
   if (cubes > 1099511627776.0) return fail(VMC_E_STRAT, "ng^dim = %.3g exceeds 2^40", cubes);
   g->ng = ng;
+  ++g->version;
   return VMC_OK;
 }
 
@@ -391,7 +401,9 @@ int vmc_iterate(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
     P.A.cube_max = g->cube_max;
     kind |= KIND_CMAX;
   }
-  return launch_sample(g, P, kind, static_cast<hipStream_t>(stream));
+  rc = launch_sample(g, P, kind, static_cast<hipStream_t>(stream));
+  if (rc == VMC_OK) g->fwd_version = g->version;
+  return rc;
 }
 
 int vmc_iterate_adjoint(vmc_grid_t g, int integrand, const double* theta, int ntheta, int64_t ncall,
@@ -400,6 +412,11 @@ int vmc_iterate_adjoint(vmc_grid_t g, int integrand, const double* theta, int nt
   int rc = plan_launch(g, integrand, theta, ntheta, ncall, seed, it, flags, P);
   if (rc) return rc;
   if (P.ks->ngrad <= 0) return fail(VMC_E_INTEGRAND, "integrand %d has no parameters to differentiate", integrand);
+  if (g->fwd_version != g->version)
+    return fail(VMC_E_GRID, g->fwd_version == 0
+                                ? "no forward pass on this grid state: run vmc_iterate first"
+                                : "the grid changed (refine, set_edges, reset, stratify or bind) since the "
+                                  "forward pass this adjoint pass would differentiate");
   return launch_sample(g, P, KIND_ADJ, static_cast<hipStream_t>(stream));
 }
 
@@ -409,7 +426,26 @@ int vmc_iterate_fused(vmc_grid_t g, int integrand, const double* theta, int nthe
   int rc = plan_launch(g, integrand, theta, ntheta, ncall, seed, it, flags, P);
   if (rc) return rc;
   if (P.ks->ngrad <= 0) return fail(VMC_E_INTEGRAND, "integrand %d has no parameters to differentiate", integrand);
-  return launch_sample(g, P, KIND_FUSED, static_cast<hipStream_t>(stream));
+  rc = launch_sample(g, P, KIND_FUSED, static_cast<hipStream_t>(stream));
+  if (rc == VMC_OK) g->fwd_version = g->version;
+  return rc;
+}
+
+int vmc_grid_version(vmc_grid_t g, uint64_t* version) {
+  if (!g || !version) return fail(VMC_E_INVALID, "NULL argument");
+  *version = g->version;
+  return VMC_OK;
+}
+
+int vmc_integrand_info(int integrand, int dim, uint32_t flags, int* ntheta, int* ngrad) {
+  if (integrand < VMC_CONST || integrand > VMC_WHEL) return fail(VMC_E_INTEGRAND, "unknown integrand id %d", integrand);
+  const bool fp64 = flags & VMC_FLAG_FP64;
+  const KernelSet* ks = lookup_kernels(integrand, dim, fp64);
+  if (!ks)
+    return fail(VMC_E_DIM, "integrand %d is not compiled for dim %d (%s)", integrand, dim, fp64 ? "fp64" : "fp32");
+  if (ntheta) *ntheta = ks->ntheta;
+  if (ngrad) *ngrad = ks->ngrad;
+  return VMC_OK;
 }
 
 int vmc_timing(vmc_grid_t g, int enable, double* total_ms, int64_t* launches) {
@@ -435,6 +471,7 @@ int vmc_refine(vmc_grid_t g, double alpha, void* stream) {
   if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(VMC_E_INVALID, "alpha %g must be finite and >= 0", alpha);
   hipLaunchKernelGGL(k_refine, dim3(g->d), dim3(kBlock), 0, static_cast<hipStream_t>(stream), g->edges, g->table,
                      g->bins, g->d, g->N, alpha);
+  ++g->version;
   HIP_TRY(hipGetLastError(), "k_refine launch");
   return VMC_OK;
 }
@@ -470,6 +507,7 @@ int vmc_set_edges(vmc_grid_t g, const double* host_edges, void* stream) {
       if (!(e[j + 1] > e[j])) return fail(VMC_E_GRID, "axis %d: edges not strictly increasing at bin %d", a, j);
   }
   hipStream_t st = static_cast<hipStream_t>(stream);
+  ++g->version;
   HIP_TRY(hipMemcpyAsync(g->edges, host_edges, sizeof(double) * g->d * (g->N + 1), hipMemcpyHostToDevice, st),
           "edges H2D");
   const int n = g->d * g->N;
@@ -480,26 +518,31 @@ int vmc_set_edges(vmc_grid_t g, const double* host_edges, void* stream) {
 }
 
 int vmc_dump_samples(vmc_grid_t g, int integrand, const double* theta, int ntheta, int64_t ncall, uint64_t seed,
-                     uint32_t it, uint32_t flags, int64_t s0, int64_t count, uint32_t* words, void* w, void* f,
-                     void* jac, void* stream) {
+                     uint32_t it, uint32_t flags, int64_t s0, int64_t count, uint32_t* words, uint8_t* bins, void* w,
+                     void* f, void* jac, void* grad, void* stream) {
   Plan P;
   int rc = plan_launch(g, integrand, theta, ntheta, ncall, seed, it, flags, P);
   if (rc) return rc;
   if (s0 < 0 || count < 0 || static_cast<uint64_t>(s0 + count) > P.A.ncall)
     return fail(VMC_E_INVALID, "sample range [%lld, %lld) outside [0, %llu)", (long long)s0, (long long)(s0 + count),
                 (unsigned long long)P.A.ncall);
+  if (grad && P.ks->ngrad <= 0)
+    return fail(VMC_E_INTEGRAND, "integrand %d has no parameters to differentiate", integrand);
   if (count == 0) return VMC_OK;
   DumpArgs D{};
   D.A = P.A;
   D.s0 = static_cast<uint64_t>(s0);
   D.count = static_cast<uint64_t>(count);
   D.words = words;
+  D.bins = bins;
   D.w = w;
   D.f = f;
   D.jac = jac;
+  D.grad = grad;
   void* args[] = {&D};
   const uint64_t grid = (D.count + kBlock - 1) / kBlock;
-  HIP_TRY(hipLaunchKernel(P.ks->dump, dim3(static_cast<unsigned>(grid)), dim3(kBlock), args, P.lds,
+  HIP_TRY(hipLaunchKernel(grad ? P.ks->dump_grad : P.ks->dump, dim3(static_cast<unsigned>(grid)), dim3(kBlock), args,
+                          P.lds,
                           static_cast<hipStream_t>(stream)),
           "dump kernel launch");
   return VMC_OK;

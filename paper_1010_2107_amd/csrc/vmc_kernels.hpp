@@ -334,7 +334,8 @@ __device__ __forceinline__ F block_setup(const double* theta) {
 // hardware dispatcher balances the blocks over the CUs.
 // ---------------------------------------------------------------------------
 template <class F, int KIND>
-__global__ __launch_bounds__(kBlock) void k_plain(const SampleArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(StagedTraits<F>::value ? 3 : 1)))
+void k_plain(const SampleArgs A) {
   using T = typename F::T;
   constexpr int D = F::D;
   constexpr int NG = (KIND & KIND_ADJ) ? F::NGRAD : 0;
@@ -743,13 +744,17 @@ void k_strat(const SampleArgs A) {
 struct DumpArgs {
   SampleArgs A;
   uint64_t s0, count;
-  uint32_t* words;
+  uint32_t* words;  // [count][D]
+  uint8_t* bins;    // [count][D] bin index per axis
   void* w;
   void* f;
   void* jac;
+  void* grad;  // [count][NGRAD] df/dtheta_p
 };
 
-template <class F>
+// GRAD: also the per-sample gradients (a kernel of its own, so that the
+// forward dump keeps the code, and the weights, of the accumulating kernels)
+template <class F, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_dump(const DumpArgs P) {
   using T = typename F::T;
   constexpr int D = F::D;
@@ -780,6 +785,8 @@ __global__ __launch_bounds__(kBlock) void k_dump(const DumpArgs P) {
     make_point<T, D, false>(A, tab, w, cc, j, x, jac);
   }
   T g[F::NGRAD + 1];
+#pragma unroll
+  for (int q = 0; q <= F::NGRAD; ++q) g[q] = T(0);
   T fv;
   if constexpr (StagedTraits<F>::value) {
     // The sample kernels hand the stage-1 state to stage 2 through LDS or a
@@ -792,17 +799,25 @@ __global__ __launch_bounds__(kBlock) void k_dump(const DumpArgs P) {
     F::store_state(st, sw, 1, 0);
 #pragma unroll
     for (int i = 0; i < StagedTraits<F>::words; ++i) asm volatile("" : "+v"(sw[i]));
-    fv = pass ? fn.template stage2<false>(F::load_state(sw, 1, 0), g) : T(0);
+    fv = pass ? fn.template stage2<GRAD>(F::load_state(sw, 1, 0), g) : T(0);
   } else {
-    fv = fn.template eval<false>(x, g);
+    fv = fn.template eval<GRAD>(x, g);
   }
   if (P.words) {
 #pragma unroll
     for (int a = 0; a < D; ++a) P.words[i * D + a] = w[a];
   }
+  if (P.bins) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) P.bins[i * D + a] = static_cast<uint8_t>(j[a]);
+  }
   if (P.w) static_cast<T*>(P.w)[i] = fv * jac;
   if (P.f) static_cast<T*>(P.f)[i] = fv;
   if (P.jac) static_cast<T*>(P.jac)[i] = jac;
+  if constexpr (GRAD) {
+#pragma unroll
+    for (int q = 0; q < F::NGRAD; ++q) static_cast<T*>(P.grad)[i * F::NGRAD + q] = g[q];
+  }
 }
 
 }  // namespace vmc

@@ -130,19 +130,44 @@ constexpr double low_coef(int j) {
   return j == K - 2 ? K + 1.0 : (j == K - 1 ? -static_cast<double>(K) : 0.0);
 }
 
+// t, u = 1 - t, and t in FP64 (the resonance variable is formed from it)
 template <typename T>
 struct TU {
   T t, u;
+  double t64;
 };
 
+// In the FP32 build the Newton step evaluates the residual in FP64: the FP32
+// residual is limited by its own rounding (final error 1-3 ulps), while the
+// FP64 one leaves the step's quadratic error, (K-1)/2 times the square of
+// the start's 1.5e-4, i.e. 3e-8 relative.  The derivative and its
+// reciprocal stay FP32 (their error enters the step multiplied by the
+// start's error).  The FP64 build takes three all-FP64 steps.
 template <int K, typename T>
 __device__ __forceinline__ TU<T> mass_fraction(T r) {
+  constexpr bool F32 = sizeof(T) == 4;
   if constexpr (K == 1) {
     const T s = vsqrt(T(1) - r);
-    return TU<T>{r * vrcp(T(1) + s), s};
+    const T t = r * vrcp(T(1) + s);
+    if constexpr (!F32) {
+      return TU<T>{t, s, t};
+    } else {
+      // one step on F(t) = 2t - t^2 = r (low side) or on u^2 = 1 - r (high side, u = 1 - t)
+      const double rd = static_cast<double>(r);
+      const double inv = static_cast<double>(vrcp(T(2) * s));
+      double t64;
+      if (r < T(0.5)) {
+        const double tt = static_cast<double>(t);
+        t64 = tt - fma(tt, 2.0 - tt, -rd) * inv;
+      } else {
+        const double uu = static_cast<double>(s);
+        t64 = 1.0 - (uu - fma(uu, uu, rd - 1.0) * inv);
+      }
+      return TU<T>{static_cast<T>(t64), static_cast<T>(1.0 - t64), t64};
+    }
   } else {
     static_assert(K >= kMassStartMinK && K <= kMassStartMaxK, "no start polynomial for this k");
-    constexpr int ITERS = sizeof(T) == 4 ? 1 : 3;
+    constexpr int ITERS = F32 ? 1 : 3;
     constexpr int row = K - kMassStartMinK;
     const bool lo = r < T(0.5);
     const T q = T(1) - r;  // exact for r >= 1/2
@@ -160,19 +185,39 @@ __device__ __forceinline__ TU<T> mass_fraction(T r) {
     T h[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) h[j] = lo ? T(low_coef<K>(j)) : T(comp_coef<K>(j + 2));
-#pragma unroll
-    for (int it = 0; it < ITERS; ++it) {
-      T H = h[K - 1], Hd = T(0);
+    if constexpr (F32) {
+      // residual in FP64, derivative in FP32
+      const double vd = static_cast<double>(v);
+      double H = lo ? low_coef<K>(K - 1) : comp_coef<K>(K + 1);
+      T Hs = h[K - 1], Hd = T(0);
 #pragma unroll
       for (int j = K - 2; j >= 0; --j) {
-        Hd = fma(Hd, v, H);
-        H = fma(H, v, h[j]);
+        H = fma(H, vd, lo ? low_coef<K>(j) : comp_coef<K>(j + 2));
+        Hd = fma(Hd, v, Hs);
+        Hs = fma(Hs, v, h[j]);
       }
-      const T res = fma(v * v, H, -target);
-      const T dP = v * fma(v, Hd, T(2) * H);  // > 0 inside (0, 1]; 0 at v = 0 where res = 0
-      v = fmin(fmax(v - res * vrcp(fmax(dP, T(1e-30))), T(0)), T(1));
+      const double res = fma(vd * vd, H, -static_cast<double>(target));
+      const T dP = v * fma(v, Hd, T(2) * Hs);  // > 0 inside (0, 1]; 0 at v = 0 where res = 0
+      double v64 = vd - res * static_cast<double>(vrcp(fmax(dP, T(1e-30))));
+      v64 = fmin(fmax(v64, 0.0), 1.0);
+      const double t64 = lo ? v64 : 1.0 - v64;
+      return lo ? TU<T>{static_cast<T>(v64), static_cast<T>(1.0 - v64), t64}
+                : TU<T>{static_cast<T>(t64), static_cast<T>(v64), t64};
+    } else {
+#pragma unroll
+      for (int it = 0; it < ITERS; ++it) {
+        T H = h[K - 1], Hd = T(0);
+#pragma unroll
+        for (int j = K - 2; j >= 0; --j) {
+          Hd = fma(Hd, v, H);
+          H = fma(H, v, h[j]);
+        }
+        const T res = fma(v * v, H, -target);
+        const T dP = v * fma(v, Hd, T(2) * H);  // > 0 inside (0, 1]; 0 at v = 0 where res = 0
+        v = fmin(fmax(v - res * vrcp(fmax(dP, T(1e-30))), T(0)), T(1));
+      }
+      return lo ? TU<T>{v, T(1) - v, v} : TU<T>{T(1) - v, v, T(1) - v};
     }
-    return lo ? TU<T>{v, T(1) - v} : TU<T>{T(1) - v, v};
   }
 }
 
@@ -195,28 +240,52 @@ __device__ __forceinline__ int ilogb_(double x) { return __builtin_amdgcn_frexp_
 __device__ __forceinline__ float ldexp_(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
 __device__ __forceinline__ double ldexp_(double x, int e) { return __builtin_amdgcn_ldexp(x, e); }
 
+// The resonance variable in FP64.  The Breit-Wigner factor depends on
+// m^2 - M^2, and its logarithmic slope in m^2 reaches m^2 / (M Gamma), about
+// 38 for the W: a relative error of m^2 reaches the weight 38 times larger.
+// In FP32 the partonic energy s = S exp(L (1 - x0 x1)) alone carries up to
+// 2e-6 (the exponent's argument, up to |ln tau0| ~ 11, is rounded) and each
+// mass fraction 1e-7 to 2e-7, which would put errors of up to 1e-4 into the
+// heaviest weights.  The FP32 build therefore forms m^2 = s t_2 ... t_{n-1}
+// in FP64 from the same FP32 point: s with an FP64 exponential, each t_i
+// from the Newton step with the FP64 residual (mass_fraction), the product
+// in FP64, and dm = m^2 - M^2 rounded once to FP32.  Everything else (the
+// momenta, cuts and matrix element) stays FP32.
+struct Resonance64 {
+  double m2;   // in: s; then s t_2 ... t_i
+  double Mv2;  // M^2
+  float dm;    // out: m^2 - M^2 of the last pair
+};
+
+template <int NOUT, int X0, int I, bool RES64, typename T, int D>
+__device__ __forceinline__ void mass_chain(const T (&x)[D], T (&Mi)[NOUT + 1], T (&Ui)[NOUT + 1],
+                                           Resonance64& res) {
+  if constexpr (I <= NOUT - 1) {
+    const TU<T> tu = mass_fraction<NOUT - I, T>(x[X0 + I - 2]);
+    Mi[I] = Mi[I - 1] * vsqrt(tu.t);
+    Ui[I] = tu.u;
+    if constexpr (RES64) res.m2 *= tu.t64;
+    mass_chain<NOUT, X0, I + 1, RES64>(x, Mi, Ui, res);
+  } else if constexpr (RES64) {
+    float dm = static_cast<float>(res.m2 - res.Mv2);
+    asm volatile("" : "+v"(dm));  // formed here, where its inputs are live anyway
+    res.dm = dm;
+  }
+}
+
 // RAMBO on diet (Plaetzer, arXiv:1308.2922): NOUT massless momenta in the
 // rest frame of a system of mass rs from x[X0 .. X0 + 3 NOUT - 5]: first
 // the masses M_2 > ... > M_{NOUT-1} (x[X0 + i - 2] fixes M_i), then one
 // direction (cos theta, phi) per two-body step i = 1..NOUT-1, each boosted
 // by the current Q_i.  Mi[1..NOUT] and Ui[i] = 1 - M_i^2 / M_{i-1}^2 are
 // returned with the momenta p[0..NOUT-1].
-template <int NOUT, int X0, int I, typename T, int D>
-__device__ __forceinline__ void mass_chain(const T (&x)[D], T (&Mi)[NOUT + 1], T (&Ui)[NOUT + 1]) {
-  if constexpr (I <= NOUT - 1) {
-    const TU<T> tu = mass_fraction<NOUT - I, T>(x[X0 + I - 2]);
-    Mi[I] = Mi[I - 1] * vsqrt(tu.t);
-    Ui[I] = tu.u;
-    mass_chain<NOUT, X0, I + 1>(x, Mi, Ui);
-  }
-}
-
-template <int NOUT, int X0, typename T, int D>
+// RES64: also form the resonance variable in FP64 (res.m2 = s on entry).
+template <int NOUT, int X0, bool RES64, typename T, int D>
 __device__ __forceinline__ void rambo_diet(const T (&x)[D], T rs, T (&Mi)[NOUT + 1], T (&Ui)[NOUT + 1],
-                                           T (&p)[NOUT][4]) {
+                                           T (&p)[NOUT][4], Resonance64& res) {
   Mi[1] = rs;
   Ui[1] = T(0);
-  mass_chain<NOUT, X0, 2>(x, Mi, Ui);
+  mass_chain<NOUT, X0, 2, RES64>(x, Mi, Ui, res);
   Mi[NOUT] = T(0);
   Ui[NOUT] = T(1);
   T Q[4] = {rs, T(0), T(0), T(0)};
@@ -250,6 +319,38 @@ __device__ __forceinline__ void rambo_diet(const T (&x)[D], T rs, T (&Mi)[NOUT +
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) p[NOUT - 1][c] = Q[c];
+}
+
+// e^a in FP64 for a <= 0 of moderate size (here a >= ln tau0 > -30): with
+// z = a log2 e = n + f, n = rint(z), |f| <= 1/2, e^a = 2^n e^y with
+// y = f ln 2, |y| <= 0.347, and e^y from its Taylor series to y^11 (the
+// remainder is below 3e-14 relative).
+__device__ __forceinline__ double exp_neg_fp64(double a) {
+  const double z = a * 1.4426950408889634;
+  const double n = rint(z);
+  const double y = (z - n) * 0.6931471805599453;
+  double p = 1.0 / 39916800.0;  // 1/11!
+  p = fma(p, y, 1.0 / 3628800.0);
+  p = fma(p, y, 1.0 / 362880.0);
+  p = fma(p, y, 1.0 / 40320.0);
+  p = fma(p, y, 1.0 / 5040.0);
+  p = fma(p, y, 1.0 / 720.0);
+  p = fma(p, y, 1.0 / 120.0);
+  p = fma(p, y, 1.0 / 24.0);
+  p = fma(p, y, 1.0 / 6.0);
+  p = fma(p, y, 0.5);
+  p = fma(p, y, 1.0);
+  p = fma(p, y, 1.0);
+  return __builtin_amdgcn_ldexp(p, static_cast<int>(n));
+}
+
+// The partonic energy s = S exp(L (1 - x0 x1)) in FP64 from the FP32 point
+// (x0 x1 and 1 - x0 x1 are exact in FP64); L = ln tau0 and S the collider
+// energy squared, each given as an FP32 (high, low) pair.
+__device__ __forceinline__ double shat_fp64(float x0, float x1, float Lh, float Ll, float Sh, float Sl) {
+  const double L = static_cast<double>(Lh) + static_cast<double>(Ll);
+  const double S = static_cast<double>(Sh) + static_cast<double>(Sl);
+  return S * exp_neg_fp64(L * (1.0 - static_cast<double>(x0) * static_cast<double>(x1)));
 }
 
 // Massless light-cone components E +- pz, rapidity and pT of a momentum:
@@ -288,6 +389,9 @@ struct WJetsF {
   T L, LL, sqrtS, pre;
   T M, Mv2, MG, MGpi, M2G2, invM, invG, two_np_over_g, twoMG2;
   T ptmin2, etamax, dr2;
+  // FP64 constants of the resonance variable as (high, low) FP32 pairs (a
+  // double member makes the compiler keep the whole functor in registers)
+  T L_lo, S_hi, S_lo, Mv2_lo;
 
   __device__ void setup(const double* th) {
     const double pi = 3.14159265358979323846;
@@ -303,6 +407,10 @@ struct WJetsF {
     LL = static_cast<T>(Ld * Ld);
     sqrtS = static_cast<T>(sS);
     ptmin2 = static_cast<T>(ptm * ptm);
+    L_lo = static_cast<T>(Ld - static_cast<double>(L));
+    S_hi = static_cast<T>(S);
+    S_lo = static_cast<T>(S - static_cast<double>(S_hi));
+    Mv2_lo = FULL ? static_cast<T>(th[0] * th[0] - static_cast<double>(static_cast<T>(th[0] * th[0]))) : T(0);
     if (FULL) {
       const double Md = th[0], Gd = th[1], gd = th[2];
       // f = flux Jx g^(2NP) BW [2 s^4 sum 1/prod s] cV s^(n-2) / (2 s)
@@ -326,12 +434,12 @@ struct WJetsF {
   // The evaluation in two stages so that a kernel can queue the samples
   // that pass the cuts and run the colour sum on full waves: stage 1 maps
   // x to momenta, applies the cuts and keeps the scaled invariants y_kl of
-  // the coloured set (upper triangle), m_enu^2 and the prefactor; stage 2
-  // forms |M|^2 and f from them.
+  // the coloured set (upper triangle), m_enu^2 - M^2 and the prefactor;
+  // stage 2 forms |M|^2 and f from them.
   static constexpr int NY = MC * (MC - 1) / 2;
   struct State {
     T y[NY];
-    T m2, pref;  // pref = pre s^(n-3) flux Jacobian s^4 / c^m
+    T dm, pref;  // dm = m_enu^2 - M^2; pref = pre s^(n-3) flux Jacobian s^4 / c^m
   };
   static constexpr int kStateWords = NY + 2;
   static constexpr bool kStaged = FULL && sizeof(T) == 4;  // the queue holds FP32
@@ -339,14 +447,14 @@ struct WJetsF {
   __device__ __forceinline__ static void store_state(const State& st, float* q, int stride, int e) {
 #pragma unroll
     for (int i = 0; i < NY; ++i) q[i * stride + e] = static_cast<float>(st.y[i]);
-    q[NY * stride + e] = static_cast<float>(st.m2);
+    q[NY * stride + e] = static_cast<float>(st.dm);
     q[(NY + 1) * stride + e] = static_cast<float>(st.pref);
   }
   __device__ __forceinline__ static State load_state(const float* q, int stride, int e) {
     State st;
 #pragma unroll
     for (int i = 0; i < NY; ++i) st.y[i] = static_cast<T>(q[i * stride + e]);
-    st.m2 = static_cast<T>(q[NY * stride + e]);
+    st.dm = static_cast<T>(q[NY * stride + e]);
     st.pref = static_cast<T>(q[(NY + 1) * stride + e]);
     return st;
   }
@@ -369,7 +477,14 @@ struct WJetsF {
     // ---- RAMBO on diet: masses M_1 = sqrt(s) > M_2 > ... > M_{n-1} > M_n = 0
     T Mi[NOUT + 1], Ui[NOUT + 1];
     T p[NOUT][4];
-    rambo_diet<NOUT, 2>(x, rs, Mi, Ui, p);
+    constexpr bool RES64 = sizeof(T) == 4;
+    Resonance64 res{};
+    if constexpr (RES64) {
+      res.m2 = shat_fp64(x[0], x[1], L, L_lo, S_hi, S_lo);
+      res.Mv2 = static_cast<double>(Mv2) + static_cast<double>(Mv2_lo);
+    }
+    rambo_diet<NOUT, 2, RES64>(x, rs, Mi, Ui, p, res);
+    if constexpr (RES64) st.dm = res.dm;
 
     // ---- visible particles: partons 0..NP-1 and the electron NP
     constexpr int NV = NP + 1;
@@ -439,7 +554,7 @@ struct WJetsF {
         const T sij = fma(lp[i], lm[j], lm[i] * lp[j]) - T(2) * (p[i][1] * p[j][1] + p[i][2] * p[j][2]);
         st.y[k++] = c * vrcp(sij);  // (2+i, 2+j)
       }
-    st.m2 = Mi[NOUT - 1] * Mi[NOUT - 1];
+    if constexpr (sizeof(T) == 8) st.dm = fma(Mi[NOUT - 1], Mi[NOUT - 1], -Mv2);
     const T s2 = shat * shat;
     st.pref = ((pre * spow) * fluxjac) * ldexp_(s2 * s2, -ce * MC);
     return true;
@@ -468,7 +583,7 @@ struct WJetsF {
       ptsum = cycle_sum<MC, T>(y);
     }
     // ---- Breit-Wigner in m_enu^2 = M_{n-1}^2 (e nu are the last pair)
-    const T dm = st.m2 - Mv2;
+    const T dm = st.dm;
     const T invD = vrcp(fma(dm, dm, M2G2));
     const T f = st.pref * (MGpi * invD) * ptsum;
     if (GRAD) {

@@ -14,6 +14,7 @@ struct KernelSet {
   const void* plain[4];  // indexed by KIND (1 fwd, 2 adj, 3 fused)
   const void* strat[8];  // and KIND_FWD | KIND_CMAX
   const void* dump;
+  const void* dump_grad;  // the dump with per-sample gradients (NULL without parameters)
   const void* spring;
   int queue_bytes;        // LDS of the plain kernels' stage-2 queue (0: unstaged)
   int strat_queue_bytes;  // LDS of the stratified forward kernels' queue and slots (0: unstaged)
@@ -33,8 +34,9 @@ KernelSet make_kernel_set() {
     s.strat[KIND_ADJ] = reinterpret_cast<const void*>(&k_strat<F, KIND_ADJ>);
     s.plain[KIND_FUSED] = reinterpret_cast<const void*>(&k_plain<F, KIND_FUSED>);
     s.strat[KIND_FUSED] = reinterpret_cast<const void*>(&k_strat<F, KIND_FUSED>);
+    s.dump_grad = reinterpret_cast<const void*>(&k_dump<F, true>);
   }
-  s.dump = reinterpret_cast<const void*>(&k_dump<F>);
+  s.dump = reinterpret_cast<const void*>(&k_dump<F, false>);
   s.spring = reinterpret_cast<const void*>(&k_spring<F>);
   s.queue_bytes = queue_bytes<F>();
   s.strat_queue_bytes = strat_queue_bytes<F>();

@@ -112,6 +112,7 @@ struct WHelF {
 
   T L, LL, sqrtS, pre, ptmin2, eta_mu, eta_g, ptij2;
   T M, Mv2, M2G2, twoMG2, m2M2G, two_ng_over_g;
+  T L_lo, S_hi, S_lo, Mv2_lo;  // FP64 constants of the resonance variable as FP32 (high, low) pairs
 
   __device__ void setup(const double* th) {
     const double pi = 3.14159265358979323846;
@@ -128,6 +129,10 @@ struct WHelF {
     L = static_cast<T>(Ld);
     LL = static_cast<T>(Ld * Ld);
     sqrtS = static_cast<T>(sS);
+    L_lo = static_cast<T>(Ld - static_cast<double>(L));
+    S_hi = static_cast<T>(S);
+    S_lo = static_cast<T>(S - static_cast<double>(S_hi));
+    Mv2_lo = static_cast<T>(Md * Md - static_cast<double>(static_cast<T>(Md * Md)));
     ptmin2 = static_cast<T>(ptm * ptm);
     eta_mu = static_cast<T>(th[5]);
     eta_g = static_cast<T>(th[6]);
@@ -161,7 +166,7 @@ struct WHelF {
   // maps x to momenta and applies the cuts; stage 2 forms |M|^2 and f.
   struct State {
     T p[NOUT][4];  // g_1..g_NG, mu+, nu in the partonic frame
-    T Eh, m2, pref, hel;  // sqrt(s)/2, m_munu^2, prefactor, helicity configuration
+    T Eh, dm, pref, hel;  // sqrt(s)/2, m_munu^2 - M^2, prefactor, helicity configuration
   };
   static constexpr int kStateWords = 4 * NOUT + 4;
   static constexpr bool kStaged = sizeof(T) == 4;  // the queue holds FP32
@@ -172,7 +177,7 @@ struct WHelF {
 #pragma unroll
       for (int c = 0; c < 4; ++c) q[(4 * i + c) * stride + e] = static_cast<float>(st.p[i][c]);
     q[(4 * NOUT + 0) * stride + e] = static_cast<float>(st.Eh);
-    q[(4 * NOUT + 1) * stride + e] = static_cast<float>(st.m2);
+    q[(4 * NOUT + 1) * stride + e] = static_cast<float>(st.dm);
     q[(4 * NOUT + 2) * stride + e] = static_cast<float>(st.pref);
     q[(4 * NOUT + 3) * stride + e] = static_cast<float>(st.hel);
   }
@@ -183,7 +188,7 @@ struct WHelF {
 #pragma unroll
       for (int c = 0; c < 4; ++c) st.p[i][c] = static_cast<T>(q[(4 * i + c) * stride + e]);
     st.Eh = static_cast<T>(q[(4 * NOUT + 0) * stride + e]);
-    st.m2 = static_cast<T>(q[(4 * NOUT + 1) * stride + e]);
+    st.dm = static_cast<T>(q[(4 * NOUT + 1) * stride + e]);
     st.pref = static_cast<T>(q[(4 * NOUT + 2) * stride + e]);
     st.hel = static_cast<T>(q[(4 * NOUT + 3) * stride + e]);
     return st;
@@ -199,7 +204,14 @@ struct WHelF {
     const T fluxjac = LL * x[0] * (om * om * om) * vrcp(h);
     const T yb = T(0.5) * (la - lb);
     T Mi[NOUT + 1], Ui[NOUT + 1];
-    rambo_diet<NOUT, 2>(x, rs, Mi, Ui, st.p);
+    constexpr bool RES64 = sizeof(T) == 4;
+    Resonance64 res{};
+    if constexpr (RES64) {
+      res.m2 = shat_fp64(x[0], x[1], L, L_lo, S_hi, S_lo);
+      res.Mv2 = static_cast<double>(Mv2) + static_cast<double>(Mv2_lo);
+    }
+    rambo_diet<NOUT, 2, RES64>(x, rs, Mi, Ui, st.p, res);
+    if constexpr (RES64) st.dm = res.dm;
     const auto& p = st.p;
 
     // ---- cuts: gluons 0..NG-1, the muon NG
@@ -234,7 +246,7 @@ struct WHelF {
 #pragma unroll
     for (int i = 0; i < NG; ++i) spow *= shat;  // s^(n-3) from V_n / (2 s), s from |A|^2
     st.Eh = T(0.5) * rs;
-    st.m2 = Mi[NOUT - 1] * Mi[NOUT - 1];
+    if constexpr (sizeof(T) == 8) st.dm = fma(Mi[NOUT - 1], Mi[NOUT - 1], -Mv2);
     st.pref = (pre * spow) * fluxjac;
     // the gluon helicity configuration, floor(x 2^NG)
     const int hel = static_cast<int>(x[D - 1] * T(1 << NG));
@@ -314,7 +326,7 @@ struct WHelF {
       }
     }
     // ---- W propagator in m_munu^2 = M_{n-1}^2 (mu nu are the last pair)
-    const T dm = st.m2 - Mv2;
+    const T dm = st.dm;
     const T invD = vrcp(fma(dm, dm, M2G2));
     const T f = st.pref * (cs * invD);
     if (GRAD) {

@@ -29,10 +29,13 @@ class Result:
 
 
 def integrate(integrand, dim, nbins, theta, ncall, itmx, seed, alpha=1.5, ng=1, itmx2=0, acc=0.0, fp64=False,
-              grid: Grid | None = None, it0=0, stream=None, cube_max: torch.Tensor | None = None) -> Result:
+              grid: Grid | None = None, it0=0, stream=None, cube_max: torch.Tensor | None = None,
+              callback=None) -> Result:
     """cube_max (BASES only): a float64 device buffer of ng^dim entries that
     receives each cube's largest weight over the integration phase, the
-    input of SPRING event generation."""
+    input of SPRING event generation.  callback(grid, k), if given, runs on
+    the host before the sample pass of iteration k (k counts both phases),
+    e.g. to log, checkpoint or replace the grid."""
     g = grid if grid is not None else Grid(dim, nbins)
     assert (g.dim, g.nbins) == (dim, nbins)
     g.reset(stream)
@@ -49,6 +52,8 @@ def integrate(integrand, dim, nbins, theta, ncall, itmx, seed, alpha=1.5, ng=1, 
                 cube_max.zero_()
                 g.bind_cube_max(cube_max)
         for _ in range(nit):
+            if callback is not None:
+                callback(g, k)
             g.iterate(integrand, th, ncall, seed, it, fp64=fp64, stream=stream)
             hist[k] = g.scal[L.S_I:L.S_VAR + 1]
             k += 1

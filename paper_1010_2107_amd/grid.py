@@ -34,6 +34,9 @@ class Grid:
         h = ctypes.c_void_p()
         L.call("vmc_create", self.dim, self.nbins, ctypes.byref(h))
         self._h = h
+        # held by the instance: at interpreter exit the module globals may
+        # already be gone when __del__ runs
+        self._destroy = L.lib().vmc_destroy
         kw = dict(device=self.device)
         self.edges = torch.zeros((self.dim, self.nbins + 1), dtype=torch.float64, **kw)
         self.table = torch.zeros((self.dim, self.nbins, 2), dtype=torch.float32, **kw)
@@ -50,8 +53,9 @@ class Grid:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and L._lib is not None:
-            L._lib.vmc_destroy(h)
+        destroy = getattr(self, "_destroy", None)
+        if h is not None and destroy is not None:
+            destroy(h)
             self._h = None
 
     @property
@@ -127,6 +131,13 @@ class Grid:
                     var=s[L.S_VAR], n_eff=int(s[L.S_NEFF]), n_zero=int(s[L.S_NZERO]), niter=int(s[L.S_NITER]), Ibar=s[L.S_IBAR],
                     sigbar=s[L.S_SIGBAR], chi2dof=s[L.S_CHI2])
 
+    def version(self) -> int:
+        """Grid-state version: advanced by bind, reset, stratify, refine and
+        set_edges (an adjoint pass needs the version of its forward pass)."""
+        v = ctypes.c_uint64()
+        L.call("vmc_grid_version", self._h, ctypes.byref(v))
+        return v.value
+
     def grad_result(self, ngrad: int) -> dict:
         g = self.scal[L.S_GRAD:L.S_GRAD + 5 * ngrad].cpu().numpy().reshape(ngrad, 5)
         return dict(gsum=g[:, 0], gsumsq=g[:, 1], gV=g[:, 2], grad=g[:, 3], grad_var=g[:, 4])
@@ -141,29 +152,40 @@ class Grid:
         assert e.shape == (self.dim, self.nbins + 1)
         L.call("vmc_set_edges", self._h, e.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream))
 
-    def dump_into(self, integrand, theta, ncall, seed, it, s0, words=None, w=None, f=None, jac=None, stream=None):
+    def dump_into(self, integrand, theta, ncall, seed, it, s0, words=None, w=None, f=None, jac=None, bins=None,
+                  grad=None, stream=None):
         """Per-sample dump into caller tensors (device; any may be None):
-        words [count][dim] int32, w / f / jac [count] float32 or float64
-        (float64 selects the FP64 instantiation)."""
-        outs = [t for t in (words, w, f, jac) if t is not None]
+        words [count][dim] int32, bins [count][dim] uint8, w / f / jac
+        [count] and grad [count][ngrad], float32 or float64 (float64 selects
+        the FP64 instantiation)."""
+        outs = [t for t in (words, bins, w, f, jac, grad) if t is not None]
         count = outs[0].shape[0] if outs else 0
-        fp64 = any(t.dtype == torch.float64 for t in (w, f, jac) if t is not None)
+        assert all(t.shape[0] == count and t.is_contiguous() for t in outs)
+        fl = [t for t in (w, f, jac, grad) if t is not None]
+        fp64 = any(t.dtype == torch.float64 for t in fl)
+        assert all(t.dtype == (torch.float64 if fp64 else torch.float32) for t in fl)
+        assert words is None or (words.dtype == torch.int32 and tuple(words.shape) == (count, self.dim))
+        assert bins is None or (bins.dtype == torch.uint8 and tuple(bins.shape) == (count, self.dim))
+        if grad is not None:
+            ngrad = L.integrand_info(integrand, self.dim, fp64)[1]
+            assert tuple(grad.shape) == (count, ngrad), (tuple(grad.shape), ngrad)
         th = self.theta_tensor(theta)
         L.call("vmc_dump_samples", self._h, int(integrand), _ptr(th if th.numel() else None), th.numel(),
                int(ncall), int(seed), int(it), L.FLAG_FP64 if fp64 else 0, int(s0), int(count), _ptr(words),
-               _ptr(w), _ptr(f), _ptr(jac), _stream_ptr(stream))
+               _ptr(bins), _ptr(w), _ptr(f), _ptr(jac), _ptr(grad), _stream_ptr(stream))
 
-    def dump(self, integrand, theta, ncall, seed, it, s0, count, fp64=False, stream=None):
-        """Per-sample words, w = f J, f and J of samples [s0, s0+count)."""
+    def dump(self, integrand, theta, ncall, seed, it, s0, count, fp64=False, want_grad=False, stream=None):
+        """Per-sample words, bin indices, w = f J, f, J (and df/dtheta with
+        want_grad) of samples [s0, s0+count)."""
         dt = torch.float64 if fp64 else torch.float32
         kw = dict(device=self.device)
-        words = torch.zeros((count, self.dim), dtype=torch.int32, **kw)
-        w = torch.zeros(count, dtype=dt, **kw)
-        f = torch.zeros(count, dtype=dt, **kw)
-        jac = torch.zeros(count, dtype=dt, **kw)
-        th = self.theta_tensor(theta)
-        L.call("vmc_dump_samples", self._h, int(integrand), _ptr(th if th.numel() else None), th.numel(),
-               int(ncall), int(seed), int(it), L.FLAG_FP64 if fp64 else 0, int(s0), int(count), _ptr(words),
-               _ptr(w), _ptr(f), _ptr(jac), _stream_ptr(stream))
-        return dict(words=words.cpu().numpy().view(np.uint32), w=w.cpu().numpy(), f=f.cpu().numpy(),
-                    jac=jac.cpu().numpy())
+        out = dict(words=torch.zeros((count, self.dim), dtype=torch.int32, **kw),
+                   bins=torch.zeros((count, self.dim), dtype=torch.uint8, **kw),
+                   w=torch.zeros(count, dtype=dt, **kw), f=torch.zeros(count, dtype=dt, **kw),
+                   jac=torch.zeros(count, dtype=dt, **kw))
+        if want_grad:
+            out["grad"] = torch.zeros((count, L.integrand_info(integrand, self.dim, fp64)[1]), dtype=dt, **kw)
+        self.dump_into(integrand, theta, ncall, seed, it, s0, stream=stream, **out)
+        res = {k: v.cpu().numpy() for k, v in out.items()}
+        res["words"] = res["words"].view(np.uint32)
+        return res

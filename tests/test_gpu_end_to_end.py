@@ -35,6 +35,48 @@ def test_configuration_within_three_sigma(w):
     assert r.var[-1] < r.var[0]
 
 
+@pytest.mark.parametrize("ng", [1, 4])
+def test_bases_two_phase_driver_matches_oracle(ng):
+    """The driver's two phases (paper Sec. 3.1 and 6.1: ITMX1 iterations that
+    re-optimise the grid, then ITMX2 iterations on the frozen grid whose
+    results alone are combined), FP64 instantiation, against the oracle's
+    driver.  Before each sample pass the GPU grid is set to the edges the
+    oracle sampled on, so both sides see the same samples: every I_k and
+    var_k, the final Ibar, sigbar and chi^2/dof agree to summation order,
+    the grid stays frozen in phase 2, and the phase-1 estimates are shown
+    to be left out of the combination."""
+    announce(f"bases two-phase driver ng={ng}")
+    d, N, theta, seed, itmx1, itmx2 = 8, 128, (1 / 3, 2 / 3, 0.1), 4321, 3, 3
+    ncall = 4**8 * 4 + 9 if ng > 1 else 200_003
+    ref = O.integrate(W.DGAUSS, d, N, theta, ncall, itmx1, seed, ng=ng, itmx2=itmx2)
+    assert len(ref.edges_seq) == itmx1 + itmx2
+    # phase 2 samples one frozen grid: the grid of the last refinement
+    for k in range(itmx1 + 1, itmx1 + itmx2):
+        assert np.array_equal(ref.edges_seq[k], ref.edges_seq[itmx1])
+    seen = []
+
+    def sync(grid, k):
+        if k <= itmx1:  # phase 2 must not move the grid: no sync there
+            grid.set_edges(ref.edges_seq[k])
+        seen.append(grid.get_edges())
+
+    r = integrate(W.DGAUSS, d, N, theta, ncall, itmx1, seed, ng=ng, itmx2=itmx2, fp64=True, callback=sync)
+    for k in range(itmx1 + 1, itmx1 + itmx2):  # the GPU grid stayed frozen in phase 2
+        assert np.array_equal(seen[k], seen[itmx1])
+    assert np.max(np.abs(r.grid.get_edges() - ref.edges)) <= 1e-12
+    for k in range(itmx1 + itmx2):
+        assert rel(r.I[k], ref.I_all[k]) <= 1e-12, k
+        assert rel(r.var[k], ref.var_all[k]) <= 1e-10, k
+    assert rel(r.Ibar, ref.Ibar) <= 1e-12
+    assert rel(r.sigbar, ref.sigbar) <= 1e-10
+    assert abs(r.chi2dof - ref.chi2dof) <= 1e-9
+    assert r.niter == itmx2
+    assert r.n_eff == (itmx1 + itmx2) * (ncall - ncall % 4**8 if ng > 1 else ncall)
+    # combining all iterations instead gives a different answer at this precision
+    Iall, sall, _ = O.combine(ref.I_all, ref.var_all)
+    assert abs(Iall - r.Ibar) > 1e3 * 1e-12 * abs(r.Ibar) or abs(sall - r.sigbar) > 1e3 * 1e-10 * r.sigbar
+
+
 ADJ_CASES = [
     ("gauss_d4", W.GAUSS, 4, 50, (0.45, 0.12), 200_003, 1),
     ("dgauss_d8_bases", W.DGAUSS, 8, 128, (1 / 3, 2 / 3, 0.1), 4**8 * 4 + 9, 4),
@@ -56,6 +98,7 @@ def test_adjoint_fp64_matches_oracle(case):
     g.stratify(ng)
     g.set_edges(edges)
     P = len(theta) if iid != W.GAUSS_AXES else d + 1
+    g.iterate(iid, theta, ncall, 31, 4, fp64=True)  # the forward pass the adjoint differentiates
     g.adjoint(iid, theta, ncall, 31, 4, fp64=True)
     got = g.grad_result(P)
     ref = O.iterate(iid, edges, theta, ncall, 31, 4, ng=ng, want_grad=True)
@@ -81,6 +124,7 @@ def test_adjoint_fp32_matches_oracle(case):
     g.stratify(ng)
     g.set_edges(edges)
     P = len(theta) if iid != W.GAUSS_AXES else d + 1
+    g.iterate(iid, theta, ncall, 31, 4)
     g.adjoint(iid, theta, ncall, 31, 4)
     got = g.grad_result(P)
     ref = O.iterate(iid, edges, theta, ncall, 31, 4, ng=ng, want_grad=True)
@@ -100,6 +144,7 @@ def test_adjoint_vs_central_differences_common_random_numbers():
     g = Grid(w.dim, w.nbins)
     g.stratify(w.ng)
     g.set_edges(edges)
+    g.iterate(w.integrand, w.theta, ncall, 5, 3, fp64=True)
     g.adjoint(w.integrand, w.theta, ncall, 5, 3, fp64=True)
     G = g.grad_result(3)["grad"]
     smp = O.eval_samples(w.integrand, edges, w.theta, ncall, 5, 3, 0, 4**8 * 8, ng=w.ng)
@@ -126,6 +171,7 @@ def test_adjoint_statistics_against_closed_forms():
     for it in range(6):
         g.iterate(w.integrand, w.theta, 1_000_000, 77, it)
         g.refine(1.5)
+    g.iterate(w.integrand, w.theta, 4**8 * 60, 77, 6)
     g.adjoint(w.integrand, w.theta, 4**8 * 60, 77, 6)
     r = g.grad_result(3)
     z = np.abs(r["grad"]) / np.sqrt(r["grad_var"])
@@ -137,6 +183,7 @@ def test_adjoint_statistics_against_closed_forms():
     for it in range(6):
         g.iterate(W.GAUSS_AXES, th, 500_000, 3, it)
         g.refine(1.5)
+    g.iterate(W.GAUSS_AXES, th, 4_000_000, 3, 6)
     g.adjoint(W.GAUSS_AXES, th, 4_000_000, 3, 6)
     r = g.grad_result(6)
     hh = 0.5 * (special.erf((1 - c) / s) + special.erf(c / s))

@@ -8,13 +8,15 @@ Tolerances:
     W propagator's slope carries that into f); cut decisions agree except
     within 1e-9 of a threshold; the helicity choice floor(x 2^n) agrees
     except where x 2^n is within 1e-12 of an integer.
-  * FP32 integrand: median per-sample error <= 1e-5, 99th percentile
-    <= 2e-4, contribution-weighted <= 2e-5; iteration sums S1 1e-5, S2 2e-5,
-    bin plane 0 1e-5 norm-wise.  Plane 1 (sum w^2) 5e-5 norm-wise: the
-    diagrams cancel against each other (gauge cancellations) when a gluon
-    is close to a beam (|eta| up to 5), so FP32 rounding of the momenta is
-    amplified by up to e^eta in a few large weights (per-sample tail up to
-    1e-2), and the squared plane is dominated by exactly those weights.
+  * FP32 integrand, compared with the oracle evaluated at the same point
+    (the point as the FP32 grid map forms it, oracle.point32): median
+    per-sample error <= 1e-5, 99th percentile <= 2e-4, contribution-weighted
+    <= 1e-5; iteration sums S1 1e-5, S2 2e-5, bin planes 1e-5 (sum w) and
+    2e-5 (sum w^2, squaring doubles each weight's relative error), all
+    norm-wise.  The distance to the oracle at the FP64 point is printed as
+    well: it adds the effect of rounding the point to FP32, which the
+    W propagator amplifies (its logarithmic slope in m^2 reaches
+    m^2 / (M Gamma) ~ 38) and which no FP32 integrand avoids.
     Cut decisions and helicity choices may differ only within 1e-4 of a
     threshold.
   * The whel2 configuration (d = 11, 1e7 x 15) against an independent-seed
@@ -88,7 +90,7 @@ def test_fp32_per_sample(d):
     g = Grid(d, N)
     g.set_edges(e)
     got = g.dump(W.WHEL, TH, ncall, 1234, 5, 2_000_000, count)
-    ref = O.eval_samples(W.WHEL, e, TH, ncall, 1234, 5, 2_000_000, count)
+    ref = O.eval_samples(W.WHEL, e, TH, ncall, 1234, 5, 2_000_000, count, fp32_point=True)
     ok = ~_hel_edge(ref["x"], n, 1e-6)
     both = (got["f"] != 0) & (ref["f"] != 0) & ok
     r = np.abs(got["f"][both] - ref["f"][both]) / np.abs(ref["f"][both])
@@ -99,7 +101,8 @@ def test_fp32_per_sample(d):
     for i in np.nonzero(((got["f"] != 0) != (ref["f"] != 0)) & ok)[0]:
         assert whel_cut_margin(ref["x"][i], TH) < 1e-4, i
     wsum = np.sum(np.abs(got["w"][both] - ref["w"][both])) / np.sum(np.abs(ref["w"][ok]))
-    assert wsum <= 2e-5, wsum
+    print(f"d={d} contribution-weighted error {wsum:.2e}")
+    assert wsum <= 1e-5, wsum
 
 
 @pytest.mark.parametrize("d,ncall", [(8, 1_000_003), (11, 1_000_003)])
@@ -111,14 +114,16 @@ def test_iteration_sums_same_grid(d, ncall):
     g.set_edges(e)
     g.iterate(W.WHEL, TH, ncall, 1234, 9)
     r = g.result()
-    ref = O.iterate(W.WHEL, e, TH, ncall, 1234, 9)
-    print(f"d={d} S1 rel {rel(r['S1'], ref['S1']):.2e} S2 rel {rel(r['S2'], ref['S2']):.2e}")
+    ref = O.iterate(W.WHEL, e, TH, ncall, 1234, 9, fp32_point=True)
+    r64 = O.iterate(W.WHEL, e, TH, ncall, 1234, 9)
+    b = g.bins.cpu().numpy()
+    for name, o in (("fp32 point", ref), ("fp64 point", r64)):
+        print(f"d={d} vs oracle at the {name}: S1 {rel(r['S1'], o['S1']):.2e} S2 {rel(r['S2'], o['S2']):.2e} "
+              f"plane 0 {normwise(b[0], o['bins'][0]):.2e} plane 1 {normwise(b[1], o['bins'][1]):.2e}")
     assert rel(r["S1"], ref["S1"]) <= 1e-5
     assert rel(r["S2"], ref["S2"]) <= 2e-5
-    b = g.bins.cpu().numpy()
-    print(f"d={d} bins plane 0 {normwise(b[0], ref['bins'][0]):.2e} plane 1 {normwise(b[1], ref['bins'][1]):.2e}")
     assert normwise(b[0], ref["bins"][0]) <= 1e-5
-    assert normwise(b[1], ref["bins"][1]) <= 5e-5
+    assert normwise(b[1], ref["bins"][1]) <= 2e-5
     # FP64 instantiation, plain and stratified, forward and adjoint sums
     for ng, nc in ((1, 200_003), (2, 2 ** d * 40 + 3)):
         g = Grid(d, N)

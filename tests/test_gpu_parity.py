@@ -121,6 +121,31 @@ def test_fp32_iteration_matches_oracle_on_same_grid(case):
     assert r["nonfinite"] == 0
 
 
+@pytest.mark.parametrize("d,N,ng", [(1, 50, 1), (4, 64, 1), (4, 50, 5), (4, 50, 3), (8, 64, 3), (1, 64, 7)])
+def test_fp32_point_matches_oracle_point32(d, N, ng):
+    """The FP32 grid map (table of FP32 lower edges and scaled widths, one
+    fused multiply-add with the in-bin offset) gives bit for bit the point
+    the oracle forms in its FP32-point mode: f = x_0 of the FP32 integrand
+    equals the oracle's x_0, plain and stratified (ng dividing N or not),
+    on a random grid.  The FP32 parity tests of the physics integrands
+    compare against the oracle at exactly these points."""
+    announce(f"fp32 point d={d} N={N} ng={ng}")
+    rng = np.random.default_rng(10 * d + ng)
+    w = rng.gamma(0.8, size=(d, N)) + 1e-3
+    e = np.concatenate([np.zeros((d, 1)), np.cumsum(w, axis=1)], axis=1)
+    e /= e[:, -1:]
+    e[:, -1] = 1.0
+    ncall = max(ng ** d * 3, 20_000) + 11
+    g = Grid(d, N)
+    g.stratify(ng)
+    g.set_edges(e)
+    count = ncall - ncall % ng ** d if ng > 1 else ncall
+    got = g.dump(W.LINEAR, (), ncall, 2024, 3, 0, count)
+    ref = O.eval_samples(W.LINEAR, e, (), ncall, 2024, 3, 0, count, ng=ng, fp32_point=True)
+    assert np.array_equal(got["f"].astype(np.float64), ref["x"][:, 0])
+    assert np.array_equal(got["bins"].astype(np.int32), ref["j"])
+
+
 def test_random_words_bit_exact():
     for (d, seed, it, ncall) in ((4, 1234, 0, 10_000), (8, 1234, 19, 5_000_000), (10, 1234, 3, 10_000_000),
                                  (16, 1234, 19, 50_000_000), (3, 2**63 + 12345, 7, 2_000_000)):
@@ -178,6 +203,16 @@ def test_refine_matches_oracle_on_given_bins():
         assert np.array_equal(tab[..., 0], ref[:, :-1].astype(np.float32))
         # widths are stored times 2^-24 (the bin offset is a 24-bit integer)
         assert np.array_equal(tab[..., 1], (np.diff(ref, axis=1) * 2.0**-24).astype(np.float32))
+    # the hand-worked cases, each written out step by step from the definition
+    from tests.test_oracle_refine_combine import HAND_CASES
+    for name, case in sorted(HAND_CASES.items()):
+        edges, b2, alpha, want, _ = case()
+        N = b2.size
+        g = Grid(1, N)
+        g.set_edges(edges[None, :])
+        g.bins[1].copy_(torch.from_numpy(b2[None, :]))
+        g.refine(alpha)
+        assert np.max(np.abs(g.get_edges()[0] - want)) <= 1e-12, name
 
 
 def test_schedule_invariance():

@@ -97,6 +97,73 @@ def test_refine_concentrates_bins_where_weight_is():
     assert np.all(np.diff(out[0]) > 0)
 
 
+# Hand-worked refinements.  Each case writes out, for its own numbers, the
+# steps of the classic VEGAS re-binning (Lepage 1978): 3-point smoothing of
+# the per-bin sums of w^2 (2-point at the ends), normalisation to rho_j,
+# damping r_j = ((1 - rho_j) / (-ln rho_j))^alpha, and new edges that cut the
+# piecewise-constant density r_j / width_j into N pieces of equal weight T.
+# The bin each new edge falls into was located by hand from the cumulative
+# sums, and the rounded values were computed on paper as a check on the
+# arithmetic below.
+def _hand_case_a():
+    """N = 4, uniform edges, sums of w^2 (1, 1, 1, 5), alpha = 1.5."""
+    # smoothed: (1+1)/2, (1+1+1)/3, (1+1+5)/3, (1+5)/2 = 1, 1, 7/3, 3; sum 22/3
+    # rho = 3/22, 3/22, 7/22, 9/22
+    r1 = ((19 / 22) / math.log(22 / 3)) ** 1.5   # bins 0 and 1
+    r7 = ((15 / 22) / math.log(22 / 7)) ** 1.5   # bin 2
+    r9 = ((13 / 22) / math.log(22 / 9)) ** 1.5   # bin 3
+    T = (2 * r1 + r7 + r9) / 4
+    # cumulative sums 0, r1, 2 r1, 2 r1 + r7, 2 r1 + r7 + r9:
+    # T lies in bin 1, 2T in bin 2, 3T in bin 3
+    e1 = 0.25 + (T - r1) / r1 * 0.25
+    e2 = 0.50 + (2 * T - 2 * r1) / r7 * 0.25
+    e3 = 0.75 + (3 * T - 2 * r1 - r7) / r9 * 0.25
+    return (np.array([0.0, 0.25, 0.5, 0.75, 1.0]), np.array([1.0, 1.0, 1.0, 5.0]), 1.5,
+            np.array([0.0, e1, e2, e3, 1.0]), (0.34334, 0.61596, 0.81772))
+
+
+def _hand_case_b():
+    """N = 3, edges (0, 0.5, 0.75, 1), sums of w^2 (4, 1, 1), alpha = 1."""
+    # smoothed: (4+1)/2, (4+1+1)/3, (1+1)/2 = 5/2, 2, 1; sum 11/2
+    # rho = 5/11, 4/11, 2/11
+    r0 = (6 / 11) / math.log(11 / 5)
+    r1 = (7 / 11) / math.log(11 / 4)
+    r2 = (9 / 11) / math.log(11 / 2)
+    T = (r0 + r1 + r2) / 3
+    # cumulative sums 0, r0, r0 + r1, r0 + r1 + r2: T in bin 0, 2T in bin 1
+    e1 = 0.0 + T / r0 * 0.5
+    e2 = 0.5 + (2 * T - r0) / r1 * 0.25
+    return (np.array([0.0, 0.5, 0.75, 1.0]), np.array([4.0, 1.0, 1.0]), 1.0, np.array([0.0, e1, e2, 1.0]),
+            (0.433847, 0.702181))
+
+
+def _hand_case_c():
+    """N = 4, uniform edges, sums of w^2 (0, 0, 0, 8), alpha = 1: the first
+    two smoothed sums are zero, so no new edge may land in those bins."""
+    # smoothed: 0, 0, 8/3, 4; sum 20/3; rho = 0, 0, 2/5, 3/5; r = 0 at rho = 0
+    r2 = (3 / 5) / math.log(5 / 2)
+    r3 = (2 / 5) / math.log(5 / 3)
+    T = (r2 + r3) / 4
+    # cumulative sums 0, 0, 0, r2, r2 + r3: T in bin 2, 2T and 3T in bin 3
+    e1 = 0.50 + T / r2 * 0.25
+    e2 = 0.75 + (2 * T - r2) / r3 * 0.25
+    e3 = 0.75 + (3 * T - r2) / r3 * 0.25
+    return (np.array([0.0, 0.25, 0.5, 0.75, 1.0]), np.array([0.0, 0.0, 0.0, 8.0]), 1.0,
+            np.array([0.0, e1, e2, e3, 1.0]), (0.637238, 0.770470, 0.885236))
+
+
+HAND_CASES = {"a": _hand_case_a, "b": _hand_case_b, "c": _hand_case_c}
+
+
+@pytest.mark.parametrize("name", sorted(HAND_CASES))
+def test_refine_hand_worked(name):
+    edges, b2, alpha, want, paper_values = HAND_CASES[name]()
+    # the arithmetic above reproduces the values worked out on paper
+    assert np.allclose(want[1:-1], paper_values, atol=2e-6), want
+    got = O.refine(edges[None, :], b2[None, :], alpha)[0]
+    assert np.max(np.abs(got - want)) <= 1e-14, (got, want)
+
+
 def test_refine_rejects_bad_arguments():
     with pytest.raises(O.OracleError):
         O.refine(O.uniform_edges(1, 4), np.ones((1, 4)), -1.0)
