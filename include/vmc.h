@@ -113,8 +113,8 @@ int vmc_version(void);
  *   out[2] bins   double[2][dim][nbins]  plane 0: sum w per bin,
  *                                        plane 1: sum w^2 per bin,
  *                 followed by a library-private tail (the blocks' partial
- *                 sums in 32 copies, about 64 x the two planes, and a work
- *                 counter; zero between calls)
+ *                 sums in 32 copies, about 64 x the two planes; zero
+ *                 between calls; not used by vmc_iterate_static)
  *   out[3] scal   double[VMC_SCAL_LEN]   scalar block (layout above)
  * Errors: VMC_E_DIM, VMC_E_NBINS. */
 int vmc_workspace_sizes(int dim, int nbins, size_t out[4]);
@@ -135,8 +135,10 @@ int vmc_destroy(vmc_grid_t g);
  * sets the uniform grid).  Errors: VMC_E_INVALID (NULL handle or pointer). */
 int vmc_bind(vmc_grid_t g, double *edges, float *table, double *bins, double *scal);
 
-/* Reset to the uniform grid, clear all accumulators and the running
- * combination (stream-ordered).  Errors: VMC_E_UNBOUND, VMC_E_HIP. */
+/* Reset to the uniform grid, clear the bin sums, the scalar block and the
+ * running combination (stream-ordered); the private tail of the bins
+ * buffer is cleared before the next pass that uses it.
+ * Errors: VMC_E_UNBOUND, VMC_E_HIP. */
 int vmc_reset(vmc_grid_t g, void *stream);
 
 /* BASES-style stratification: split [0,1]^dim into ng^dim equal cubes and
@@ -159,6 +161,22 @@ int bases_stratify(vmc_grid_t g, int ng);
  * VMC_E_DIM (integrand not compiled for this dim), VMC_E_HIP. */
 int vmc_iterate(vmc_grid_t g, int integrand, const double *theta, int ntheta, int64_t ncall,
                 uint64_t seed, uint32_t it, uint32_t flags, void *stream);
+
+/* vmc_iterate for callers that cannot allocate device memory or use a
+ * workspace of their own (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same iteration, arguments
+ * and results, with the blocks' partial sums kept in a static device array
+ * of the library (32 copies of the 2 dim nbins bin sums and 64 scalar
+ * slots, room for dim 16 x 256 bins: 2.02 MiB per GPU, held until the
+ * process ends) instead of the private tail of the bound bins buffer, which
+ * then needs only double[2][dim][nbins].  No call allocates; the first on a
+ * device looks up the array's address and clears it with a kernel on
+ * `stream`, and every pass leaves it at zero.  All calls on one GPU share
+ * the array: calls that overlap in time on one GPU (on different streams or
+ * from different host threads) race and must be ordered by the caller.
+ * Errors: as vmc_iterate. */
+int vmc_iterate_static(vmc_grid_t g, int integrand, const double *theta, int ntheta, int64_t ncall,
+                       uint64_t seed, uint32_t it, uint32_t flags, void *stream);
 
 /* Per-cube maxima for SPRING (Sec. 3.1: the results of the BASES
  * integration phase feed event generation).  While a buffer is bound,

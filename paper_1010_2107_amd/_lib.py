@@ -54,6 +54,8 @@ _SIGS = {
     "vmc_reset": (_c.c_int, [_vp, _vp]),
     "bases_stratify": (_c.c_int, [_vp, _c.c_int]),
     "vmc_iterate": (_c.c_int, [_vp, _c.c_int, _vp, _c.c_int, _c.c_int64, _c.c_uint64, _c.c_uint32, _c.c_uint32, _vp]),
+    "vmc_iterate_static": (_c.c_int, [_vp, _c.c_int, _vp, _c.c_int, _c.c_int64, _c.c_uint64, _c.c_uint32, _c.c_uint32,
+                                      _vp]),
     "vmc_iterate_adjoint": (_c.c_int, [_vp, _c.c_int, _vp, _c.c_int, _c.c_int64, _c.c_uint64, _c.c_uint32,
                                        _c.c_uint32, _vp]),
     "vmc_iterate_fused": (_c.c_int, [_vp, _c.c_int, _vp, _c.c_int, _c.c_int64, _c.c_uint64, _c.c_uint32,

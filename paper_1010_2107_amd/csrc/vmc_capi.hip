@@ -92,6 +92,14 @@ struct vmc_grid_s {
 static size_t stripe_len(int d, int N) { return (static_cast<size_t>(2) * d * N + kStripeScal + 15) / 16 * 16; }
 static size_t bins_total(int d, int N) { return static_cast<size_t>(2) * d * N + kStripes * stripe_len(d, N); }
 
+// The blocks' partial sums of vmc_iterate_static live in this array instead
+// of the tail of the bound bins buffer: room for the largest grid (16 axes
+// of 256 bins), 32 copies of 2 d N bins and the scalar slots, 2.02 MiB per
+// GPU for the life of the process.  In host code `scratch` is only a
+// handle: its device address comes from hipGetSymbolAddress, per device.
+constexpr size_t kStaticScratch = static_cast<size_t>(kStripes) * ((2 * 16 * 256 + kStripeScal + 15) / 16 * 16);
+static __device__ __align__(256) double scratch[kStaticScratch];
+
 extern "C" {
 
 const char* vmc_last_error(void) { return g_last_error.c_str(); }
@@ -147,10 +155,12 @@ static int need_bound(vmc_grid_t g) {
 int vmc_reset(vmc_grid_t g, void* stream) {
   int rc = need_bound(g);
   if (rc) return rc;
+  // the published sums only: the private tail is cleared before the next
+  // pass that uses it (vmc_iterate_static callers may bind just the sums)
   hipLaunchKernelGGL(k_reset, dim3(16), dim3(kBlock), 0, static_cast<hipStream_t>(stream), g->edges, g->table,
-                     g->bins, static_cast<int>(bins_total(g->d, g->N)), g->scal, g->d, g->N);
+                     g->bins, 2 * g->d * g->N, g->scal, g->d, g->N);
   HIP_TRY(hipGetLastError(), "k_reset launch");
-  g->acc_dirty = false;
+  g->acc_dirty = true;
   ++g->version;
   return VMC_OK;
 }
@@ -311,10 +321,44 @@ int resident_blocks(const void* fn, size_t lds, int* out) {
   return VMC_OK;
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and cleared there once; every pass's
+// publish kernel leaves the copies it used at zero again.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(hipStream_t stream, double** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(VMC_E_INVALID, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    const int n = static_cast<int>(kStaticScratch);
+    hipLaunchKernelGGL(k_clear, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, static_cast<double*>(ptr),
+                       n, nullptr, 0, 0);
+    HIP_TRY(hipGetLastError(), "k_clear launch");
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return VMC_OK;
+}
+
 // One sample pass: blocks add their partial sums into kStripes copies; the
 // publish kernel then adds the copies up and forms the estimate.  The
-// copies are zero between passes (cleared here after a bind).
-int launch_sample(vmc_grid_t g, const Plan& P, int kind, hipStream_t stream) {
+// copies are zero between passes (cleared here after a bind).  With
+// static_copies the copies are the library's own device array, not the
+// tail of the bound bins buffer.
+int launch_sample(vmc_grid_t g, Plan& P, int kind, hipStream_t stream, bool static_copies = false) {
+  if (static_copies) {
+    if (static_cast<size_t>(kStripes) * P.A.stripe_len > kStaticScratch)
+      return fail(VMC_E_NBINS, "dim x nbins needs %zu doubles of partial sums, the static array holds %zu",
+                  static_cast<size_t>(kStripes) * P.A.stripe_len, kStaticScratch);
+    int rc = static_scratch(stream, &P.A.stripes);
+    if (rc) return rc;
+  }
   const void* fn = P.strat ? P.ks->strat[kind] : P.ks->plain[kind];
   if (!fn) return fail(VMC_E_INTEGRAND, "integrand has no parameters to differentiate");
   size_t lds = P.lds;
@@ -353,7 +397,7 @@ int launch_sample(vmc_grid_t g, const Plan& P, int kind, hipStream_t stream) {
   if (A.ntiles > 0x7fffffffULL) return fail(VMC_E_SCHEDULE, "%llu tiles: too many", (unsigned long long)A.ntiles);
   const uint64_t grid = A.ntiles;
   const int nb = 2 * g->d * g->N;
-  if (g->acc_dirty) {
+  if (g->acc_dirty && !static_copies) {
     const int n = static_cast<int>(bins_total(g->d, g->N)) - nb;
     hipLaunchKernelGGL(k_clear, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, P.A.stripes, n, g->scal,
                        0, 0);
@@ -402,6 +446,24 @@ int vmc_iterate(vmc_grid_t g, int integrand, const double* theta, int ntheta, in
     kind |= KIND_CMAX;
   }
   rc = launch_sample(g, P, kind, static_cast<hipStream_t>(stream));
+  if (rc == VMC_OK) g->fwd_version = g->version;
+  return rc;
+}
+
+int vmc_iterate_static(vmc_grid_t g, int integrand, const double* theta, int ntheta, int64_t ncall, uint64_t seed,
+                       uint32_t it, uint32_t flags, void* stream) {
+  Plan P;
+  int rc = plan_launch(g, integrand, theta, ntheta, ncall, seed, it, flags, P);
+  if (rc) return rc;
+  int kind = KIND_FWD;
+  if (P.strat && g->cube_max) {
+    if (static_cast<uint64_t>(g->cube_max_n) < P.A.M)
+      return fail(VMC_E_INVALID, "cube-maximum buffer holds %lld cubes, the stratification has %u",
+                  (long long)g->cube_max_n, P.A.M);
+    P.A.cube_max = g->cube_max;
+    kind |= KIND_CMAX;
+  }
+  rc = launch_sample(g, P, kind, static_cast<hipStream_t>(stream), true);
   if (rc == VMC_OK) g->fwd_version = g->version;
   return rc;
 }

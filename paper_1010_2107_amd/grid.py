@@ -103,6 +103,11 @@ class Grid:
         """Steps 2-4 of one iteration plus its estimate (stream-ordered)."""
         return self._run("vmc_iterate", integrand, theta, ncall, seed, it, fp64, stream)
 
+    def iterate_static(self, integrand, theta, ncall, seed, it, fp64=False, stream=None):
+        """As iterate, with the blocks' partial sums in the library's static
+        device array (vmc_iterate_static: no allocation, no workspace)."""
+        return self._run("vmc_iterate_static", integrand, theta, ncall, seed, it, fp64, stream)
+
     def adjoint(self, integrand, theta, ncall, seed, it, fp64=False, stream=None):
         return self._run("vmc_iterate_adjoint", integrand, theta, ncall, seed, it, fp64, stream)
 
