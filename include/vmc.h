@@ -360,14 +360,17 @@ int vmc_batch_timing(vmc_batch_t b, int enable, double *total_ms, int64_t *launc
  * uniform in the cube's y-range mapped through the (frozen) grid, and keeps
  * the point when u g_c < w = f J.  Kept points are distributed as f(x) dx
  * where w <= g_c; trials with w > g_c are kept and counted as overflows.
- * The envelope is integer: g_c = q_c gmax/2^20 with q_c = ceil(wmax_c /
- * gmax 2^20), so the cube choice is exact integer arithmetic.  Trial t of
+ * The envelope is integer: g_c = q_c h gmax/2^20 with q_c = ceil(wmax_c /
+ * gmax 2^20) and a headroom h >= 1 over the recorded maxima (which, being
+ * maxima of a finite sample, underestimate a cube's largest weight), so the
+ * cube choice is exact integer arithmetic.  Trial t of
  * pass p draws Philox words with counter (t mod 2^32, group | 2 << 8, p,
  * t div 2^32): words 0..dim-1 place the point, words dim and dim+1 form
  * the 64-bit cube choice r64 (low, high), word dim+2 the acceptance
  * uniform.  The grid must be stratified (ng >= 2, ng^dim <= 2^28).
  *
- * State buffer (8-byte slots): 0 one quantum (double), 1 gmax (double),
+ * State buffer (8-byte slots): 0 one quantum h gmax / 2^20 (double),
+ * 1 gmax (double),
  * 2 T = sum q_c, 3 envelope integral T quantum / ng^dim (double; the
  * keep rate is about I / this), 4 log2 of the guide size, 5 ng^dim,
  * 8 trials run, 9 trials kept, 10 overflows, 11 next event slot. */
@@ -386,11 +389,13 @@ int vmc_batch_timing(vmc_batch_t b, int enable, double *total_ms, int64_t *launc
 int spring_workspace_sizes(vmc_grid_t g, size_t out[3]);
 
 /* Build the envelope from cube_max (ng^dim doubles, e.g. filled through
- * bases_cube_max): zeroes the state's counters.  Synchronous on `stream`.
- * Errors: VMC_E_STRAT, VMC_E_INVALID, VMC_E_SPRING (a +Inf maximum, or no
- * positive one), VMC_E_HIP. */
-int spring_setup(vmc_grid_t g, const double *cube_max, uint64_t *prefix, uint32_t *guide, uint64_t *state,
-                 void *stream);
+ * bases_cube_max) with headroom h (g_c = h x the cube's quantised maximum;
+ * 1 keeps the recorded maxima, more trades keep rate for fewer overflows):
+ * zeroes the state's counters.  Synchronous on `stream`.
+ * Errors: VMC_E_STRAT, VMC_E_INVALID (also h < 1 or not finite),
+ * VMC_E_SPRING (a +Inf maximum, or no positive one), VMC_E_HIP. */
+int spring_setup(vmc_grid_t g, const double *cube_max, double headroom, uint64_t *prefix, uint32_t *guide,
+                 uint64_t *state, void *stream);
 
 /* Zero the trial, keep, overflow and slot counters (stream-ordered). */
 int spring_clear_counts(uint64_t *state, void *stream);

@@ -85,7 +85,7 @@ _SIGS = {
     "vmc_probe_fp32_fma": (_c.c_int, [_c.c_int, _c.c_int, _c.POINTER(_c.c_double), _vp]),
     "bases_cube_max": (_c.c_int, [_vp, _vp, _c.c_int64]),
     "spring_workspace_sizes": (_c.c_int, [_vp, _c.POINTER(_c.c_size_t)]),
-    "spring_setup": (_c.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "spring_setup": (_c.c_int, [_vp, _vp, _c.c_double, _vp, _vp, _vp, _vp]),
     "spring_clear_counts": (_c.c_int, [_vp, _vp]),
     "spring_generate": (_c.c_int, [_vp, _c.c_int, _vp, _c.c_int, _vp, _vp, _vp, _c.c_uint64, _c.c_uint32,
                                    _c.c_int64, _c.c_int64, _c.c_int64, _vp, _vp, _c.c_uint32, _vp]),

@@ -652,12 +652,14 @@ int spring_workspace_sizes(vmc_grid_t g, size_t out[3]) {
   return VMC_OK;
 }
 
-int spring_setup(vmc_grid_t g, const double* cube_max, uint64_t* prefix, uint32_t* guide, uint64_t* state,
-                 void* stream) {
+int spring_setup(vmc_grid_t g, const double* cube_max, double headroom, uint64_t* prefix, uint32_t* guide,
+                 uint64_t* state, void* stream) {
   SpringShape S;
   int rc = spring_shape(g, S);
   if (rc) return rc;
   if (!cube_max || !prefix || !guide || !state) return fail(VMC_E_INVALID, "a device buffer is NULL");
+  if (!(headroom >= 1.0) || !std::isfinite(headroom))
+    return fail(VMC_E_INVALID, "headroom %g must be finite and >= 1", headroom);
   g->sp_prefix = nullptr;
   g->sp_guide = nullptr;
   g->sp_state = nullptr;
@@ -666,7 +668,7 @@ int spring_setup(vmc_grid_t g, const double* cube_max, uint64_t* prefix, uint32_
   hipLaunchKernelGGL(k_sp_init, dim3(1), dim3(64), 0, st, state, S.M, S.kbits);
   hipLaunchKernelGGL(k_sp_gmax, dim3(gblocks), dim3(kBlock), 0, st, cube_max, S.M, state);
   hipLaunchKernelGGL(k_sp_blocksum, dim3(static_cast<unsigned>(S.nblk)), dim3(kBlock), 0, st, cube_max, S.M, state);
-  hipLaunchKernelGGL(k_sp_scan_blocks, dim3(1), dim3(kBlock), 0, st, state, S.nblk);
+  hipLaunchKernelGGL(k_sp_scan_blocks, dim3(1), dim3(kBlock), 0, st, state, S.nblk, headroom);
   hipLaunchKernelGGL(k_sp_scan, dim3(static_cast<unsigned>(S.nblk)), dim3(kBlock), 0, st, cube_max, S.M, state,
                      prefix);
   const unsigned kblocks = static_cast<unsigned>(std::min<uint64_t>((S.K + kBlock) / kBlock, 4096));

@@ -4,9 +4,10 @@
 //
 // The integration phase records the largest weight w = f J of every cube.
 // The envelope is constant on a cube and held as an integer number q_c of
-// quanta (q_c = ceil(wmax_c / gmax 2^20), one quantum = gmax / 2^20), so
-// that the running sums P_c = q_0 + ... + q_{c-1} and the choice of a cube
-// are exact integer arithmetic.  A trial draws a 64-bit integer r64, takes
+// quanta (q_c = ceil(wmax_c / gmax 2^20), one quantum = h gmax / 2^20 with
+// a headroom h >= 1 over the recorded maxima), so that the running sums
+// P_c = q_0 + ... + q_{c-1} and the choice of a cube are exact integer
+// arithmetic.  A trial draws a 64-bit integer r64, takes
 // r = floor(r64 T / 2^64) (T = P_M) and the cube c with P_c <= r < P_{c+1},
 // places a point uniformly in the cube's y-range, maps it through the
 // frozen grid and keeps it when u g_c < w (g_c = q_c quanta).  Kept points
@@ -28,7 +29,7 @@ namespace vmc {
 // 64-bit integers elsewhere.  Slots from SP_HDR on are scratch for the
 // set-up's scan (one per scan block).
 enum : int {
-  SP_UNIT = 0,     // envelope value of one quantum, gmax / 2^20
+  SP_UNIT = 0,     // envelope value of one quantum, headroom x gmax / 2^20
   SP_GMAX = 1,     // largest cube maximum
   SP_TOTAL = 2,    // T = sum of q_c
   SP_ENV = 3,      // envelope integral T unit / M (the acceptance is about I / this)

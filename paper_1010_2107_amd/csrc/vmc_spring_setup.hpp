@@ -100,8 +100,8 @@ __global__ __launch_bounds__(kBlock) void k_sp_blocksum(const double* wmax, uint
 }
 
 // Exclusive scan of the nblk block sums in place (one block), then the
-// header: T, one quantum, the envelope integral.
-__global__ __launch_bounds__(kBlock) void k_sp_scan_blocks(uint64_t* st, uint64_t nblk) {
+// header: T, one quantum (headroom x gmax / 2^20), the envelope integral.
+__global__ __launch_bounds__(kBlock) void k_sp_scan_blocks(uint64_t* st, uint64_t nblk, double headroom) {
   __shared__ uint64_t lds[kBlock / kWave];
   uint64_t carry = 0;
   for (uint64_t base = 0; base < nblk; base += kBlock) {
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_sp_scan_blocks(uint64_t* st, uint64_
   }
   if (threadIdx.x == 0) {
     const double gmax = __longlong_as_double(static_cast<long long>(st[SP_GMAX]));
-    const double unit = gmax / kSpringQuanta;
+    const double unit = gmax / kSpringQuanta * headroom;
     st[SP_TOTAL] = carry;
     st[SP_UNIT] = static_cast<uint64_t>(__double_as_longlong(unit));
     st[SP_ENV] = static_cast<uint64_t>(

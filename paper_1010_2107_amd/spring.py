@@ -28,10 +28,11 @@ class Spring:
         self.state = torch.zeros(sizes[2] // 8, dtype=torch.int64, **kw)
         self.ncubes = self.prefix.numel() - 1
 
-    def setup(self, cube_max: torch.Tensor, stream=None):
+    def setup(self, cube_max: torch.Tensor, headroom: float = 1.0, stream=None):
+        """Envelope g_c = headroom x the quantised cube maxima (headroom >= 1)."""
         assert cube_max.dtype == torch.float64 and cube_max.numel() >= self.ncubes
-        L.call("spring_setup", self.grid.handle, _ptr(cube_max), _ptr(self.prefix), _ptr(self.guide),
-               _ptr(self.state), _stream_ptr(stream))
+        L.call("spring_setup", self.grid.handle, _ptr(cube_max), float(headroom), _ptr(self.prefix),
+               _ptr(self.guide), _ptr(self.state), _stream_ptr(stream))
 
     def clear_counts(self, stream=None):
         L.call("spring_clear_counts", _ptr(self.state), _stream_ptr(stream))

@@ -30,12 +30,14 @@ def _gpu():
     require_gpu()
 
 
+@pytest.mark.parametrize("nbins", [16, 64])
 @pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
-def test_batched_matches_oracle_per_integral(fp64):
-    announce(f"batched vs oracle fp64={fp64}")
+def test_batched_matches_oracle_per_integral(fp64, nbins):
+    """nbins = 64 is the batched configuration's grid."""
+    announce(f"batched vs oracle fp64={fp64} nbins={nbins}")
     th = _thetas(DIMS)
-    b = Batch(DIMS, NCALLS, th, nbins=16)
-    edges = [O.uniform_edges(d, 16) for d in DIMS]
+    b = Batch(DIMS, NCALLS, th, nbins=nbins)
+    edges = [O.uniform_edges(d, nbins) for d in DIMS]
     tol = 1e-12 if fp64 else 1e-5
     for it in range(3):
         b.iterate(1234, it, kind=3, fp64=fp64)

@@ -97,8 +97,10 @@ def test_setup_matches_oracle(shape):
     sp = Spring(g)
     assert sp.ncubes == M
     w = _random_maxima(np.random.default_rng(M), M)
-    sp.setup(torch.from_numpy(w).cuda())
+    headroom = 1.0 + 0.25 * (M % 3)  # 1.0, 1.25 or 1.5: the quantum scales, the quanta do not
+    sp.setup(torch.from_numpy(w).cuda(), headroom)
     q_ref, unit_ref = O.spring_envelope(w)
+    unit_ref *= headroom
     h = sp.header()
     assert h["unit"] == unit_ref and h["gmax"] == np.nanmax(w) and h["total"] == int(q_ref.sum())
     assert h["ncubes"] == M and (1 << h["kbits"]) >= M and (h["kbits"] == 0 or (1 << (h["kbits"] - 1)) < M)
@@ -217,6 +219,10 @@ def test_error_paths(gauss2):
         with pytest.raises(VmcError) as ei:
             sp.setup(torch.from_numpy(bad).cuda())
         assert ei.value.name == "VMC_E_SPRING"
+    for bad_h in (0.5, float("nan"), float("inf")):
+        with pytest.raises(VmcError) as ei:
+            sp.setup(torch.from_numpy(G["wmax"]).cuda(), bad_h)
+        assert ei.value.name == "VMC_E_INVALID"
     sp.setup(torch.from_numpy(G["wmax"]).cuda())
     sp.generate(W.GAUSS_AXES, G["th"], 1, 0, 0, 100, ev)
     with pytest.raises(VmcError) as ei:
@@ -258,3 +264,65 @@ def test_bases_then_spring_physics():
     x = ev[:200].cpu().numpy().astype(np.float64)
     for xi in x:
         assert O.integrand(W.WJETS, xi, W.WJETS_THETA) > 0.0
+
+
+def test_headroom_removes_overflow_bias():
+    """A narrow 2-D Gaussian product whose cube maxima come from a short
+    integration phase (four samples per cube): many cubes' recorded maxima
+    fall short of their largest weight, so at headroom 1 a few per cent of
+    the kept events overflow and are under-represented.  With the headroom
+    set from the largest ratio of a cube's weight to its recorded maximum
+    over a dense sample of that cube (a sample of the same distribution as
+    the trials), the overflow fraction falls below 1e-3 and the kept points'
+    marginals agree with the closed form: per axis, the Pearson chi^2 over
+    the bins (of 40) of the truncated Gaussian that expect at least 5
+    events stays below its mean plus 3 standard deviations."""
+    from scipy import special
+
+    from paper_1010_2107_amd.driver import integrate
+    announce("spring headroom")
+    th, ng, d, N = (0.42, 0.55, 0.07), 8, 2, 32
+    M = ng ** d
+    buf = torch.zeros(M, dtype=torch.float64, device="cuda")
+    res = integrate(W.GAUSS_AXES, d, N, th, M * 40, 4, 17, ng=ng, itmx2=1, cube_max=buf, fp64=True)
+    g = res.grid
+    # small phase-2 run: re-record the maxima from only 4 samples per cube
+    buf.zero_()
+    g.bind_cube_max(buf)
+    g.iterate(W.GAUSS_AXES, th, M * 4, 17, 50, fp64=True)
+    g.bind_cube_max(None)
+    wmax = buf.cpu().numpy()
+    # dense sample of every cube (4096 per cube) for its largest weight
+    dense = g.dump(W.GAUSS_AXES, th, M * 4096, 99, 51, 0, M * 4096, fp64=True)["w"].reshape(4096, M)
+    ratio = np.max(dense, axis=0) / np.where(wmax > 0, wmax, np.inf)
+    sp = Spring(g)
+    ntr = 4_000_000
+    cap = 600_000
+    ev = torch.zeros((cap, d), dtype=torch.float64, device="cuda")
+    tr = torch.zeros(cap, dtype=torch.int64, device="cuda")
+    sp.setup(buf, 1.0)
+    sp.generate(W.GAUSS_AXES, th, 3, 0, 0, ntr, ev, tr, fp64=True)
+    h1 = sp.header()
+    over1 = h1["over"] / h1["kept"]
+    headroom = float(1.02 * ratio.max())
+    sp.setup(buf, headroom)
+    sp.generate(W.GAUSS_AXES, th, 3, 1, 0, ntr, ev, tr, fp64=True)
+    h = sp.header()
+    over = h["over"] / h["kept"]
+    print(f"headroom 1: overflow {over1:.4f} of kept; headroom {headroom:.2f}: {over:.2e}, kept {h['kept']}")
+    assert over1 > 0.01
+    assert over <= 1e-3
+    n = min(h["slot"], cap)
+    x = ev[:n].cpu().numpy()
+    edges = np.linspace(0.0, 1.0, 41)
+    for a in range(d):
+        c, s_ = th[a], th[2]
+        cdf = special.erf((edges - c) / s_) - special.erf(-c / s_)
+        p = np.diff(cdf) / cdf[-1]
+        cnt = np.histogram(x[:, a], bins=edges)[0]
+        use = n * p >= 5.0
+        assert cnt[~use].sum() <= max(10.0, 3.0 * n * p[~use].sum())  # the far tails stay (nearly) empty
+        chi2 = np.sum((cnt[use] - n * p[use]) ** 2 / (n * p[use]))
+        dof = int(use.sum()) - 1
+        print(f"axis {a}: chi^2 {chi2:.1f} for {dof} degrees of freedom ({n} events)")
+        assert chi2 < dof + 3 * np.sqrt(2 * dof), (a, chi2, dof)
