@@ -182,28 +182,28 @@ __device__ __forceinline__ TU<T> mass_fraction(T r) {
     }
     T v = fmin(s * (lo ? rl : rh), T(1));
     const T target = lo ? r : q;
-    T h[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) h[j] = lo ? T(low_coef<K>(j)) : T(comp_coef<K>(j + 2));
     if constexpr (F32) {
-      // residual in FP64, derivative in FP32
+      // residual in FP64, derivative in FP32 (its Horner running on the
+      // FP64 partial values rounded to FP32)
       const double vd = static_cast<double>(v);
       double H = lo ? low_coef<K>(K - 1) : comp_coef<K>(K + 1);
-      T Hs = h[K - 1], Hd = T(0);
+      T Hd = T(0);
 #pragma unroll
       for (int j = K - 2; j >= 0; --j) {
+        Hd = fma(Hd, v, static_cast<T>(H));
         H = fma(H, vd, lo ? low_coef<K>(j) : comp_coef<K>(j + 2));
-        Hd = fma(Hd, v, Hs);
-        Hs = fma(Hs, v, h[j]);
       }
       const double res = fma(vd * vd, H, -static_cast<double>(target));
-      const T dP = v * fma(v, Hd, T(2) * Hs);  // > 0 inside (0, 1]; 0 at v = 0 where res = 0
+      const T dP = v * fma(v, Hd, T(2) * static_cast<T>(H));  // > 0 inside (0, 1]; 0 at v = 0 where res = 0
       double v64 = vd - res * static_cast<double>(vrcp(fmax(dP, T(1e-30))));
       v64 = fmin(fmax(v64, 0.0), 1.0);
       const double t64 = lo ? v64 : 1.0 - v64;
       return lo ? TU<T>{static_cast<T>(v64), static_cast<T>(1.0 - v64), t64}
                 : TU<T>{static_cast<T>(t64), static_cast<T>(v64), t64};
     } else {
+      T h[K];
+#pragma unroll
+      for (int j = 0; j < K; ++j) h[j] = lo ? T(low_coef<K>(j)) : T(comp_coef<K>(j + 2));
 #pragma unroll
       for (int it = 0; it < ITERS; ++it) {
         T H = h[K - 1], Hd = T(0);
@@ -321,27 +321,18 @@ __device__ __forceinline__ void rambo_diet(const T (&x)[D], T rs, T (&Mi)[NOUT +
   for (int c = 0; c < 4; ++c) p[NOUT - 1][c] = Q[c];
 }
 
-// e^a in FP64 for a <= 0 of moderate size (here a >= ln tau0 > -30): with
-// z = a log2 e = n + f, n = rint(z), |f| <= 1/2, e^a = 2^n e^y with
-// y = f ln 2, |y| <= 0.347, and e^y from its Taylor series to y^11 (the
-// remainder is below 3e-14 relative).
+// e^a for a <= 0 of moderate size (here a >= ln tau0 > -30), with the
+// argument reduction in FP64 and the reduced exponential in FP32: with
+// z = a log2 e = n + f, n = rint(z), |f| <= 1/2, e^a = 2^n 2^f, where 2^f
+// comes from the hardware exp2 (about 1 ulp, 6e-8) of f rounded to FP32
+// (absolute error below 3e-8, i.e. 2e-8 relative in 2^f).  The FP32 path
+// rounded the whole argument instead, up to |ln tau0| ~ 11 in size, which
+// alone made 7e-7 relative error in the partonic energy.
 __device__ __forceinline__ double exp_neg_fp64(double a) {
   const double z = a * 1.4426950408889634;
   const double n = rint(z);
-  const double y = (z - n) * 0.6931471805599453;
-  double p = 1.0 / 39916800.0;  // 1/11!
-  p = fma(p, y, 1.0 / 3628800.0);
-  p = fma(p, y, 1.0 / 362880.0);
-  p = fma(p, y, 1.0 / 40320.0);
-  p = fma(p, y, 1.0 / 5040.0);
-  p = fma(p, y, 1.0 / 720.0);
-  p = fma(p, y, 1.0 / 120.0);
-  p = fma(p, y, 1.0 / 24.0);
-  p = fma(p, y, 1.0 / 6.0);
-  p = fma(p, y, 0.5);
-  p = fma(p, y, 1.0);
-  p = fma(p, y, 1.0);
-  return __builtin_amdgcn_ldexp(p, static_cast<int>(n));
+  const float e = __builtin_amdgcn_exp2f(static_cast<float>(z - n));
+  return __builtin_amdgcn_ldexp(static_cast<double>(e), static_cast<int>(n));
 }
 
 // The partonic energy s = S exp(L (1 - x0 x1)) in FP64 from the FP32 point
