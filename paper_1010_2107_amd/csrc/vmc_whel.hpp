@@ -55,39 +55,54 @@ template <typename T>
 struct Sp {  // a 2-component spinor
   Cx<T> a, b;
 };
+// A complex four-vector V held as its 2x2 block V.sigmabar =
+// [[p, lo], [hi, m]] with p = V0 + V3, m = V0 - V3, lo = V1 - i V2,
+// hi = V1 + i V2: the light-cone components are formed directly from
+// their sources, never as differences of nearly equal V0 and V3 (which for
+// momenta close to a beam lose up to (E / pT)^2 of their precision).
 template <typename T>
-struct CV {  // a complex contravariant four-vector
-  Cx<T> v[4];
+struct SB {
+  Cx<T> p, m, lo, hi;
 };
 
-// (V . sigmabar) x = [[V0+V3, V1 - i V2], [V1 + i V2, V0-V3]] x
+// (V . sigmabar) x
 template <typename T>
-__device__ __forceinline__ Sp<T> sbar(const CV<T>& V, const Sp<T>& x) {
-  const Cx<T> p = V.v[0] + V.v[3], m = V.v[0] - V.v[3];
-  const Cx<T> lo = {V.v[1].r + V.v[2].i, V.v[1].i - V.v[2].r};  // V1 - i V2
-  const Cx<T> hi = {V.v[1].r - V.v[2].i, V.v[1].i + V.v[2].r};  // V1 + i V2
-  return {p * x.a + lo * x.b, hi * x.a + m * x.b};
+__device__ __forceinline__ Sp<T> sbar(const SB<T>& V, const Sp<T>& x) {
+  return {V.p * x.a + V.lo * x.b, V.hi * x.a + V.m * x.b};
 }
 // first component only (the last vertex before v_L(p_dbar) = (r, 0))
 template <typename T>
-__device__ __forceinline__ Cx<T> sbar_top(const CV<T>& V, const Sp<T>& x) {
-  const Cx<T> p = V.v[0] + V.v[3];
-  const Cx<T> lo = {V.v[1].r + V.v[2].i, V.v[1].i - V.v[2].r};
-  return p * x.a + lo * x.b;
+__device__ __forceinline__ Cx<T> sbar_top(const SB<T>& V, const Sp<T>& x) {
+  return V.p * x.a + V.lo * x.b;
 }
 // (V . sigmabar) (0, 1): the first vertex on u_L(p_u) = (0, r)
 template <typename T>
-__device__ __forceinline__ Sp<T> sbar_u(const CV<T>& V) {
-  return {{V.v[1].r + V.v[2].i, V.v[1].i - V.v[2].r}, V.v[0] - V.v[3]};
+__device__ __forceinline__ Sp<T> sbar_u(const SB<T>& V) {
+  return {V.lo, V.m};
 }
-// propagator (P . sigma) x / P^2 for a real momentum P
+// A real momentum by its light-cone components P+ = P0 + P3, P- = P0 - P3
+// and its transverse part.
 template <typename T>
-__device__ __forceinline__ Sp<T> prop(const T (&P)[4], const Sp<T>& x) {
-  const T inv = vrcp(fma(P[0], P[0], -fma(P[1], P[1], fma(P[2], P[2], P[3] * P[3]))));
-  const T m = (P[0] - P[3]) * inv, p = (P[0] + P[3]) * inv;
-  const Cx<T> lo = {-P[1] * inv, P[2] * inv};   // -(P1 - i P2) / P^2
-  const Cx<T> hi = {-P[1] * inv, -P[2] * inv};  // -(P1 + i P2) / P^2
+struct LC {
+  T p, m, x, y;
+};
+// the propagator (P . sigma) x / P^2; every propagator here is space-like
+// with P+ >= 0 >= P-, so P^2 = P+ P- - Px^2 - Py^2 adds terms of one sign
+template <typename T>
+__device__ __forceinline__ Sp<T> prop(const LC<T>& P, const Sp<T>& x) {
+  const T inv = vrcp(fma(P.p, P.m, -fma(P.x, P.x, P.y * P.y)));
+  const T m = P.m * inv, p = P.p * inv;
+  const Cx<T> lo = {-P.x * inv, P.y * inv};   // -(P1 - i P2) / P^2
+  const Cx<T> hi = {-P.x * inv, -P.y * inv};  // -(P1 + i P2) / P^2
   return {m * x.a + lo * x.b, hi * x.a + p * x.b};
+}
+// light-cone components of a massless momentum: the larger of E +- pz
+// directly, the smaller as pT^2 over it
+template <typename T>
+__device__ __forceinline__ LC<T> massless_lc(const T (&k)[4]) {
+  const T big = k[0] + fabs(k[3]);
+  const T small = fma(k[1], k[1], k[2] * k[2]) * vrcp(big);
+  return k[3] > T(0) ? LC<T>{big, small, k[1], k[2]} : LC<T>{small, big, k[1], k[2]};
 }
 
 // left-chirality spinor of a massless momentum (p.sigmabar u = 0, |u|^2 = 2E)
@@ -146,18 +161,27 @@ struct WHelF {
   }
 
   // outgoing gluon k, helicity lam: conj of (0, (-lam e1 - i e2) / sqrt2),
-  // e1, e2 the polar and azimuthal unit vectors of k
-  __device__ __forceinline__ static CV<T> eps_out(const T (&k)[4], T pt, T lam) {
+  // e1, e2 the polar and azimuthal unit vectors of k; returned as its
+  // sigmabar block (eps^0 = 0) and its spatial components (for the dot
+  // products of the three-gluon vertex)
+  struct Eps {
+    SB<T> b;
+    Cx<T> v[3];
+  };
+  __device__ __forceinline__ static Eps eps_out(const T (&k)[4], T pt, T lam) {
     const T s = T(0.70710678118654752440);
     const T ik = vrcp(k[0]), ip = vrcp(pt);
     const T e1x = k[3] * k[1] * ik * ip, e1y = k[3] * k[2] * ik * ip, e1z = -pt * ik;
     const T e2x = -k[2] * ip, e2y = k[1] * ip;
     const T a = -lam * s;
-    CV<T> e;
-    e.v[0] = {T(0), T(0)};
-    e.v[1] = {a * e1x, s * e2x};
-    e.v[2] = {a * e1y, s * e2y};
-    e.v[3] = {a * e1z, T(0)};
+    Eps e;
+    e.v[0] = {a * e1x, s * e2x};
+    e.v[1] = {a * e1y, s * e2y};
+    e.v[2] = {a * e1z, T(0)};
+    e.b.p = e.v[2];
+    e.b.m = {-e.v[2].r, -e.v[2].i};
+    e.b.lo = {e.v[0].r + e.v[1].i, e.v[0].i - e.v[1].r};  // V1 - i V2
+    e.b.hi = {e.v[0].r - e.v[1].i, e.v[0].i + e.v[1].r};  // V1 + i V2
     return e;
   }
 
@@ -260,68 +284,82 @@ struct WHelF {
     const int hel = static_cast<int>(st.hel);
     const T Eh = st.Eh;
 
-    // ---- lepton current L = u_L(nu)^dagger sigmabar v_L(mu), sigmabar = (1, -sigma)
+    // ---- lepton current L = u_L(nu)^dagger sigmabar v_L(mu), sigmabar = (1, -sigma),
+    // as its block: L0 + L3 = 2 a1* b1, L0 - L3 = 2 a0* b0, L1 - i L2 = -2 a1* b0,
+    // L1 + i L2 = -2 a0* b1 (a = u(nu), b = v(mu))
     const Sp<T> a = weyl(p[NOUT - 1]);
     const Sp<T> b = weyl(p[NOUT - 2]);
     const Cx<T> ac0 = {a.a.r, -a.a.i}, ac1 = {a.b.r, -a.b.i};
-    const Cx<T> a0b0 = ac0 * b.a, a0b1 = ac0 * b.b, a1b0 = ac1 * b.a, a1b1 = ac1 * b.b;
-    CV<T> Lc;
-    Lc.v[0] = a0b0 + a1b1;
-    Lc.v[1] = {-(a0b1.r + a1b0.r), -(a0b1.i + a1b0.i)};
-    Lc.v[2] = {-(a0b1.i - a1b0.i), a0b1.r - a1b0.r};  // i (a0* b1 - a1* b0)
-    Lc.v[3] = a1b1 - a0b0;
+    SB<T> Lc;
+    Lc.p = T(2) * (ac1 * b.b);
+    Lc.m = T(2) * (ac0 * b.a);
+    Lc.lo = T(-2) * (ac1 * b.a);
+    Lc.hi = T(-2) * (ac0 * b.b);
 
     T cs;  // colour sum of |chain|^2
     if constexpr (NG == 0) {
       const Cx<T> A = sbar_top(Lc, Sp<T>{{T(0), T(0)}, {T(1), T(0)}});
       cs = T(3) * norm2(A);
     } else {
-      T q[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) q[c] = p[NOUT - 2][c] + p[NOUT - 1][c];
+      // light-cone components of the gluons and of q = p_mu + p_nu; each
+      // propagator momentum p_u - (...) = (...)' - p_dbar takes its + part
+      // from the particles it leaves out and its - part from those it
+      // contains, both sums of non-negative terms (p_u = (2Eh, 0) and
+      // p_dbar = (0, 2Eh) in (+, -))
+      const LC<T> lm = massless_lc(p[NOUT - 2]), ln = massless_lc(p[NOUT - 1]);
+      const LC<T> q = {lm.p + ln.p, lm.m + ln.m, lm.x + ln.x, lm.y + ln.y};
       const Sp<T> uL = sbar_u(Lc);  // W first from the u end
-      const T Pq[4] = {Eh - q[0], -q[1], -q[2], Eh - q[3]};  // p_u - q
       if constexpr (NG == 1) {
-        const T ptg = vsqrt(p[0][1] * p[0][1] + p[0][2] * p[0][2]);
-        const CV<T> e = eps_out(p[0], ptg, (hel & 1) ? T(1) : T(-1));
-        const T Pk[4] = {Eh - p[0][0], -p[0][1], -p[0][2], Eh - p[0][3]};
-        const Cx<T> A = sbar_top(Lc, prop(Pk, sbar_u(e))) + sbar_top(e, prop(Pq, uL));
+        const LC<T> k = massless_lc(p[0]);
+        const T ptg = vsqrt(fma(p[0][1], p[0][1], p[0][2] * p[0][2]));
+        const Eps e = eps_out(p[0], ptg, (hel & 1) ? T(1) : T(-1));
+        const LC<T> Pk = {q.p, -k.m, -k.x, -k.y};  // p_u - k
+        const LC<T> Pq = {k.p, -q.m, k.x, k.y};    // p_u - q
+        const Cx<T> A = sbar_top(Lc, prop(Pk, sbar_u(e.b))) + sbar_top(e.b, prop(Pq, uL));
         cs = T(4) * norm2(A);
       } else {
         const T(&k1)[4] = p[0];
         const T(&k2)[4] = p[1];
-        const T pt1 = vsqrt(k1[1] * k1[1] + k1[2] * k1[2]), pt2v = vsqrt(k2[1] * k2[1] + k2[2] * k2[2]);
-        const CV<T> e1 = eps_out(k1, pt1, (hel & 1) ? T(1) : T(-1));
-        const CV<T> e2 = eps_out(k2, pt2v, (hel & 2) ? T(1) : T(-1));
+        const LC<T> c1 = massless_lc(k1), c2 = massless_lc(k2);
+        const T pt1 = vsqrt(fma(k1[1], k1[1], k1[2] * k1[2])), pt2v = vsqrt(fma(k2[1], k2[1], k2[2] * k2[2]));
+        const Eps e1 = eps_out(k1, pt1, (hel & 1) ? T(1) : T(-1));
+        const Eps e2 = eps_out(k2, pt2v, (hel & 2) ? T(1) : T(-1));
         // off-shell gluon of the three-gluon vertex, V / K^2 with
-        // V = (e1.e2)(k2 - k1) - 2 (k2.e1) e2 + 2 (k1.e2) e1 (e^0 = 0)
-        const T K[4] = {k1[0] + k2[0], k1[1] + k2[1], k1[2] + k2[2], k1[3] + k2[3]};
-        const T iK2 = vrcp(fma(K[0], K[0], -fma(K[1], K[1], fma(K[2], K[2], K[3] * K[3]))));
+        // V = (e1.e2)(k2 - k1) - 2 (k2.e1) e2 + 2 (k1.e2) e1 (e^0 = 0), and
+        // K^2 = 2 k1.k2 = E1 E2 |k1/E1 - k2/E2|^2 (no cancellation for
+        // nearly collinear gluons)
+        const T i1 = vrcp(k1[0]), i2 = vrcp(k2[0]);
+        const T dx = fma(k1[1], i1, -k2[1] * i2), dy = fma(k1[2], i1, -k2[2] * i2), dz = fma(k1[3], i1, -k2[3] * i2);
+        const T iK2 = vrcp(k1[0] * k2[0] * fma(dx, dx, fma(dy, dy, dz * dz)));
         Cx<T> e12 = {T(0), T(0)}, k2e1 = {T(0), T(0)}, k1e2 = {T(0), T(0)};
 #pragma unroll
-        for (int c = 1; c < 4; ++c) {
+        for (int c = 0; c < 3; ++c) {
           e12 = e12 - e1.v[c] * e2.v[c];
-          k2e1 = k2e1 - k2[c] * e1.v[c];
-          k1e2 = k1e2 - k1[c] * e2.v[c];
+          k2e1 = k2e1 - k2[c + 1] * e1.v[c];
+          k1e2 = k1e2 - k1[c + 1] * e2.v[c];
         }
-        CV<T> J;
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          J.v[c] = iK2 * ((k2[c] - k1[c]) * e12 - T(2) * (k2e1 * e2.v[c]) + T(2) * (k1e2 * e1.v[c]));
-        const T Pk1[4] = {Eh - k1[0], -k1[1], -k1[2], Eh - k1[3]};
-        const T Pk2[4] = {Eh - k2[0], -k2[1], -k2[2], Eh - k2[3]};
-        const T PK[4] = {Eh - K[0], -K[1], -K[2], Eh - K[3]};
-        const T Pk1q[4] = {Pk1[0] - q[0], Pk1[1] - q[1], Pk1[2] - q[2], Pk1[3] - q[3]};
-        const T Pk2q[4] = {Pk2[0] - q[0], Pk2[1] - q[1], Pk2[2] - q[2], Pk2[3] - q[3]};
-        const Sp<T> ya = prop(Pk2, sbar_u(e2));  // gluon 2 first
-        const Sp<T> yw = prop(Pk1, sbar_u(e1));  // gluon 1 first
-        const Sp<T> yc = prop(Pq, uL);           // W first
+        const Cx<T> t2 = T(-2) * iK2 * k2e1, t1 = T(2) * iK2 * k1e2, tk = iK2 * e12;
+        const LC<T> dk = {c2.p - c1.p, c2.m - c1.m, c2.x - c1.x, c2.y - c1.y};  // k2 - k1
+        SB<T> J;
+        J.p = dk.p * tk + t2 * e2.b.p + t1 * e1.b.p;
+        J.m = dk.m * tk + t2 * e2.b.m + t1 * e1.b.m;
+        J.lo = Cx<T>{dk.x, -dk.y} * tk + t2 * e2.b.lo + t1 * e1.b.lo;
+        J.hi = Cx<T>{dk.x, dk.y} * tk + t2 * e2.b.hi + t1 * e1.b.hi;
+        const LC<T> Pk1 = {c2.p + q.p, -c1.m, -c1.x, -c1.y};                // p_u - k1
+        const LC<T> Pk2 = {c1.p + q.p, -c2.m, -c2.x, -c2.y};                // p_u - k2
+        const LC<T> PK = {q.p, -(c1.m + c2.m), -(c1.x + c2.x), -(c1.y + c2.y)};  // p_u - k1 - k2
+        const LC<T> Pk1q = {c2.p, -(c1.m + q.m), c2.x, c2.y};               // p_u - k1 - q
+        const LC<T> Pk2q = {c1.p, -(c2.m + q.m), c1.x, c1.y};               // p_u - k2 - q
+        const LC<T> Pq = {c1.p + c2.p, -q.m, c1.x + c2.x, c1.y + c2.y};     // p_u - q
+        const Sp<T> ya = prop(Pk2, sbar_u(e2.b));  // gluon 2 first
+        const Sp<T> yw = prop(Pk1, sbar_u(e1.b));  // gluon 1 first
+        const Sp<T> yc = prop(Pq, uL);             // W first
         // colour T^a1 T^a2 (gluon 1 nearer the dbar end) and T^a2 T^a1
         const Cx<T> Tt = sbar_top(Lc, prop(PK, sbar_u(J))) + sbar_top(J, yc);
-        const Cx<T> A12 = sbar_top(Lc, prop(PK, sbar(e1, ya))) + sbar_top(e1, prop(Pk2q, sbar(Lc, ya))) +
-                          sbar_top(e1, prop(Pk2q, sbar(e2, yc))) + Tt;
-        const Cx<T> A21 = sbar_top(Lc, prop(PK, sbar(e2, yw))) + sbar_top(e2, prop(Pk1q, sbar(Lc, yw))) +
-                          sbar_top(e2, prop(Pk1q, sbar(e1, yc))) - Tt;
+        const Cx<T> A12 = sbar_top(Lc, prop(PK, sbar(e1.b, ya))) + sbar_top(e1.b, prop(Pk2q, sbar(Lc, ya))) +
+                          sbar_top(e1.b, prop(Pk2q, sbar(e2.b, yc))) + Tt;
+        const Cx<T> A21 = sbar_top(Lc, prop(PK, sbar(e2.b, yw))) + sbar_top(e2.b, prop(Pk1q, sbar(Lc, yw))) +
+                          sbar_top(e2.b, prop(Pk1q, sbar(e1.b, yc))) - Tt;
         cs = T(16.0 / 3.0) * (norm2(A12) + norm2(A21)) - T(4.0 / 3.0) * fma(A12.r, A21.r, A12.i * A21.i);
       }
     }

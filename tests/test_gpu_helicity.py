@@ -16,7 +16,9 @@ Tolerances:
     norm-wise.  The distance to the oracle at the FP64 point is printed as
     well: it adds the effect of rounding the point to FP32, which the
     W propagator amplifies (its logarithmic slope in m^2 reaches
-    m^2 / (M Gamma) ~ 38) and which no FP32 integrand avoids.
+    m^2 / (M Gamma) ~ 38) and which no FP32 integrand avoids.  (The kernel
+    forms m^2 - M^2 in FP64 and the propagators and vector blocks from
+    light-cone components, so its own rounding is not amplified.)
     Cut decisions and helicity choices may differ only within 1e-4 of a
     threshold.
   * The whel2 configuration (d = 11, 1e7 x 15) against an independent-seed
