@@ -272,15 +272,17 @@ def batched_leg():
             "max_z_vs_closed_form": float(max(zs)), "all_within_3_sigma": bool(max(zs) < 3)}
 
 
-def spring_leg(trials=50_000_000, pilot=20_000_000, max_overflow=1e-3):
+def spring_leg(trials=50_000_000, pilot=20_000_000, pilot_kept=20_000, max_overflow=1e-3):
     """SPRING event generation after a BASES run whose integration phase
     records the cube maxima: trials/s and kept events/s of one
     spring_generate launch, for the double Gaussian (d=8, 4^8 cubes) and for
     W + 2 partons (d=10, 2^10 cubes).  The recorded maxima come from a finite
     sample, so some trials exceed the envelope (overflow); the envelope's
     headroom over the maxima is the smallest of a ladder whose pilot run
-    (other trial numbers) keeps overflows at or below max_overflow of the
-    kept events, and the timed run reports its overflow fraction."""
+    (other trial numbers, at least `pilot` trials and enough for about
+    pilot_kept kept events, so that a fraction of max_overflow is resolved)
+    keeps overflows at or below max_overflow of the kept events, and the
+    timed run reports its overflow fraction."""
     import torch
 
     from paper_1010_2107_amd import workloads as W
@@ -289,7 +291,7 @@ def spring_leg(trials=50_000_000, pilot=20_000_000, max_overflow=1e-3):
 
     out = {}
     cases = [(W.C2, W.C2.ncall, W.C2.ng, W.C2.itmx, W.C2.itmx2),
-             (W.C3, 2_000_000, 2, 5, 10)]
+             (W.C3, W.C3.ncall, 2, 5, 10)]
     for w, ncall, ng, itmx, itmx2 in cases:
         name = w.name if w is W.C2 else f"{w.name.split('_vegas')[0]}_bases_ng{ng}"
         buf = torch.zeros(ng ** w.dim, dtype=torch.float64, device="cuda")
@@ -300,13 +302,19 @@ def spring_leg(trials=50_000_000, pilot=20_000_000, max_overflow=1e-3):
         tr = torch.empty(cap, dtype=torch.int64, device="cuda")
         ladder = []
         headroom = None
-        for h_try in (1.0, 1.5, 2.0, 3.0, 4.0, 6.0, 8.0, 12.0, 16.0):
+        n_pilot, h_prev = pilot, None
+        for h_try in (1.0, 1.5, 2.0, 3.0, 4.0, 6.0, 8.0, 12.0, 16.0, 24.0, 32.0):
+            if h_prev is not None:
+                # the efficiency falls as 1/h: size the pilot for ~pilot_kept kept events
+                eff_next = max(ladder[-1]["efficiency"], 1e-9) * h_prev / h_try
+                n_pilot = int(min(max(pilot, pilot_kept / eff_next), 1_000_000_000))
             sp.setup(buf, h_try)
-            sp.generate(w.integrand, w.theta, 7, 100, 0, pilot, ev, tr)
+            sp.generate(w.integrand, w.theta, 7, 100, 0, n_pilot, ev, tr)
             hp = sp.header()
             frac = hp["over"] / max(hp["kept"], 1)
-            ladder.append({"headroom": h_try, "overflow_fraction_of_kept": frac,
-                           "efficiency": hp["kept"] / hp["trials"]})
+            ladder.append({"headroom": h_try, "trials": hp["trials"], "kept": hp["kept"],
+                           "overflow_fraction_of_kept": frac, "efficiency": hp["kept"] / hp["trials"]})
+            h_prev = h_try
             if frac <= max_overflow:
                 headroom = h_try
                 break
@@ -553,19 +561,21 @@ def main(argv=None):
     L.call("vmc_probe_fp32_fma", 8192, 4096, ctypes.byref(fma), stream)
     roof["fp32_fma_probe"] = {"peak_tflops": fma.value / 1e12, "frac": achieved / (fma.value / 1e12),
                               "note": "8 independent FP32 FMA chains per lane, packed FP32 off"}
-    # instruction-mix ceiling: the launch cannot be shorter than its VALU
-    # instructions at the probe's issue rate (one wave FMA = 2 x 64 flops)
+    # VALU issue estimate: the counted VALU wave instructions at the FMA
+    # probe's issue rate (one wave FMA = 2 x 64 flops per 4 cycles per SIMD).
+    # An estimate, not a bound: some instructions issue faster, so the ratio
+    # can exceed 1; near 1 it says the VALU issue is what the launch waits on.
     valu = measured_valu(w.name)
     if valu:
         issue = fma.value / 128.0
-        t_min = valu / issue
-        roof["instruction_mix"] = {
-            "valu_per_launch": valu, "min_launch_ms": t_min * 1e3, "issue_frac": t_min / (avg_ms / 1e3),
-            "ceiling_tflops": flops * n_eff / t_min / 1e12,
-            "note": "SQ_INSTS_VALU from the committed counter summary over the same 20 iterations; "
-                    "issue rate from the FMA probe"}
+        t_issue = valu / issue
+        roof["valu_issue"] = {
+            "valu_per_launch": valu, "valu_per_64_samples": valu * 64.0 / n_eff,
+            "issue_time_ms": t_issue * 1e3, "issue_time_over_launch": t_issue / (avg_ms / 1e3),
+            "note": "SQ_INSTS_VALU from the committed counter summary (same kernel sources) at the FMA probe's "
+                    "issue rate; an estimate, not a bound"}
     else:
-        roof["instruction_mix"] = None
+        roof["valu_issue"] = None
     peak = ctypes.c_double()
     L.call("vmc_probe_lds_atomics", 2048, 4096, ctypes.byref(peak), stream)
     lds_achieved = 2 * w.dim * n_eff / (avg_ms / 1e3)
