@@ -276,9 +276,12 @@ __device__ __forceinline__ void mass_chain(const T (&x)[D], T (&Mi)[NOUT + 1], T
 // RAMBO on diet (Plaetzer, arXiv:1308.2922): NOUT massless momenta in the
 // rest frame of a system of mass rs from x[X0 .. X0 + 3 NOUT - 5]: first
 // the masses M_2 > ... > M_{NOUT-1} (x[X0 + i - 2] fixes M_i), then one
-// direction (cos theta, phi) per two-body step i = 1..NOUT-1, each boosted
-// by the current Q_i.  Mi[1..NOUT] and Ui[i] = 1 - M_i^2 / M_{i-1}^2 are
-// returned with the momenta p[0..NOUT-1].
+// direction (cos theta, phi) per two-body step i = 1..NOUT-1: the massless
+// momentum of step i is boosted by the current Q_i, and the recoiling
+// system is what remains of Q_i (the boost is linear and takes Q_i's rest
+// momentum to Q_i itself, so boosting the recoil gives Q_i - p_i).
+// Mi[1..NOUT] and Ui[i] = 1 - M_i^2 / M_{i-1}^2 are returned with the
+// momenta p[0..NOUT-1].
 // RES64: also form the resonance variable in FP64 (res.m2 = s on entry).
 template <int NOUT, int X0, bool RES64, typename T, int D>
 __device__ __forceinline__ void rambo_diet(const T (&x)[D], T rs, T (&Mi)[NOUT + 1], T (&Ui)[NOUT + 1],
@@ -295,26 +298,25 @@ __device__ __forceinline__ void rambo_diet(const T (&x)[D], T rs, T (&Mi)[NOUT +
     const T rc = x[X0 + NOUT - 2 + 2 * i - 2];
     const T rp = x[X0 + NOUT - 2 + 2 * i - 1];
     const T cth = fma(T(2), rc, T(-1));
-    const T sth = T(2) * vsqrt(rc * (T(1) - rc));
+    const T sth = vsqrt(rc * fma(T(-4), rc, T(4)));  // 2 sqrt(rc (1 - rc))
     T sp, cp;
     vsincos2pi(rp, sp, cp);
     const T nx = sth * cp, ny = sth * sp, nz = cth;
     const T pr[4] = {q, q * nx, q * ny, q * nz};
-    const T qr[4] = {Mi[i] - q, -q * nx, -q * ny, -q * nz};
     if (i == 1) {
+      p[0][0] = q;
+      Q[0] = Mi[1] - q;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 1; c < 4; ++c) {
         p[0][c] = pr[c];
-        Q[c] = qr[c];
+        Q[c] = -pr[c];
       }
     } else {
       const T iM = vrcp(Mi[i]);
       const T iEM = vrcp(Q[0] + Mi[i]);
-      T qn[4];
       boost(Q, iM, iEM, pr, p[i - 1]);
-      boost(Q, iM, iEM, qr, qn);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) Q[c] = qn[c];
+      for (int c = 0; c < 4; ++c) Q[c] -= p[i - 1][c];
     }
   }
 #pragma unroll
@@ -349,7 +351,7 @@ __device__ __forceinline__ double shat_fp64(float x0, float x1, float Lh, float 
 // +-ln(larger / pT).
 template <typename T>
 struct LightCone {
-  T pt2, pt, rpt2, lp, lm, eta;
+  T pt2, pt, rpt, rpt2, lp, lm, eta;
 };
 template <typename T>
 __device__ __forceinline__ LightCone<T> light_cone(const T (&v)[4]) {
@@ -364,6 +366,7 @@ __device__ __forceinline__ LightCone<T> light_cone(const T (&v)[4]) {
   r.lm = z > T(0) ? small : big;
   r.eta = copysign(ya, z);
   r.pt = r.pt2 * rpt;
+  r.rpt = rpt;
   r.rpt2 = rpt * rpt;
   return r;
 }
@@ -479,31 +482,33 @@ struct WJetsF {
 
     // ---- visible particles: partons 0..NP-1 and the electron NP
     constexpr int NV = NP + 1;
-    T pt2[NV], pt[NV], rpt2[NV], lp[NV], lm[NV], eta[NV];
-    bool pass = true;
-    T pt2_min = T(0);  // the pT cut on the smallest pT^2: one compare instead of NV
+    T pt2[NV], rpt2[NV], lp[NV], lm[NV], eta[NV], ux[NV], uy[NV];
+    // the pT and rapidity cuts on the smallest pT^2 and the largest |eta|;
+    // fmin and fmax skip a NaN (degenerate momenta), which then fails the
+    // Delta R test below (every visible particle is in a pair there)
+    T pt2_min = T(0), yabs_max = T(0);
 #pragma unroll
     for (int j = 0; j < NV; ++j) {
       const LightCone<T> lc = light_cone(p[j]);
       pt2[j] = lc.pt2;
-      pt[j] = lc.pt;
       rpt2[j] = lc.rpt2;
       lp[j] = lc.lp;
       lm[j] = lc.lm;
       eta[j] = lc.eta;
+      ux[j] = p[j][1] * lc.rpt;  // transverse direction
+      uy[j] = p[j][2] * lc.rpt;
+      const T ya = fabs(eta[j] + yb);
       pt2_min = j == 0 ? pt2[0] : fmin(pt2_min, pt2[j]);
-      // a NaN pT^2 (degenerate momenta) is skipped by fmin, but its rapidity
-      // is NaN as well and fails here
-      pass = pass && (fabs(eta[j] + yb) < etamax);
+      yabs_max = j == 0 ? ya : fmax(yabs_max, ya);
     }
-    pass = pass && (pt2_min > ptmin2);
+    bool pass = (pt2_min > ptmin2) & (yabs_max < etamax);
     // Delta R > R: either Delta eta^2 >= R^2, or cos(Delta phi) < cos(phi0)
     // with phi0 = sqrt(R^2 - Delta eta^2) <= R.  For Delta eta^2 >= R^2 the
-    // series below is at least 1 and the scalar product never exceeds
-    // pT_i pT_j, so one comparison covers both cases.  cos(phi0) from its Taylor
-    // series in z = phi0^2: in FP64 terms to z^6 (remainder below 1e-16 for
-    // R <= 0.4), in FP32 to z^3 (for R <= 0.4 the z^4 term is below 1.6e-8,
-    // a third of an ulp of the cosine).
+    // series below is at least 1 and cos(Delta phi) never exceeds 1, so one
+    // comparison covers both cases.  cos(phi0) from its Taylor series in
+    // z = phi0^2: in FP64 terms to z^6 (remainder below 1e-16 for R <= 0.4),
+    // in FP32 to z^3 (for R <= 0.4 the z^4 term is below 1.6e-8, a third of
+    // an ulp of the cosine).
 #pragma unroll
     for (int i = 0; i < NV; ++i)
 #pragma unroll
@@ -522,8 +527,7 @@ struct WJetsF {
         c = fma(c, -z, T(1.0 / 24.0));
         c = fma(c, -z, T(1.0 / 2.0));
         c = fma(c, -z, T(1));
-        const T dot = p[i][1] * p[j][1] + p[i][2] * p[j][2];
-        pass = pass && (dot < c * pt[i] * pt[j]);
+        pass = pass & (fma(ux[i], ux[j], uy[i] * uy[j]) < c);
       }
     if (!pass) return false;
 
