@@ -54,6 +54,12 @@ def cycle_sum_flops(m):
 MAP_PER_AXIS = 5  # delta scale, fma(delta, width, lo), width*N, Jacobian product
 
 
+# The flux factor ((1-xa)(1-xb))^3 of an accepted sample: each e^x - 1
+# counted on its exp2 side (a scaling and a subtraction), their product, the
+# cube and the product with the rest of the prefactor.
+FLUX, FLUX_TRANS = 8, 2
+
+
 MASS_START_DEG = 5  # degree of the fitted start polynomial (csrc/vmc_mass_start.hpp)
 
 
@@ -77,28 +83,33 @@ def wjets(n_p: int) -> Census:
     nv = n_p + 1
     f = t = 0
     f += MAP_PER_AXIS * D
-    # parton fractions, flux x Jacobian, s^(n-3), boost rapidity; each
-    # e^x - 1 counted on its exp2 side (a scaling and a subtraction)
-    f += 21 + (n - 3)
-    t += 4
+    # parton fractions, sqrt(tau), s, s^(n-3), boost rapidity and the
+    # Jacobian factor L^2 x0 / sqrt(tau); the flux factor ((1-xa)(1-xb))^3 is
+    # formed only for accepted samples (FLUX below)
+    f += 21 - FLUX + (n - 3)
+    t += 4 - FLUX_TRANS
     # mass chain: one inverse-CDF solve per mass, then M_i = M_{i-1} sqrt(t)
     for K in range(n - 2, 0, -1):
         ff, tt = _mass_step(K)
         f += ff + 1
         t += tt + 1
-    # two-body steps: the first needs no boost, the others boost two vectors
-    f += 17 + (n - 2) * 52
+    # two-body steps: the first needs no boost (13); each other one boosts
+    # its massless momentum (17) and takes the recoil as Q - p (4), plus the
+    # direction, energy and boost factors (13)
+    f += 13 + (n - 2) * 34
     t += 3 + (n - 2) * 5
-    # visible particles: pT^2, light-cone components, rapidity, pT, cuts
-    f += 8 * nv
-    t += 4 * nv
-    # Delta R pairs: cos of the threshold angle by a 4-term Horner series
-    f += 18 * nv * (nv - 1) // 2
+    # visible particles: pT^2, light-cone components, rapidity, pT (9), the
+    # unit transverse direction (2) and |eta + y_boost| (1)
+    f += 12 * nv
+    t += 3 * nv
+    # Delta R pairs: Delta eta, z, cos of the threshold angle by its series,
+    # cos(Delta phi) from the unit directions
+    f += 12 * nv * (nv - 1) // 2
     f_fail, t_fail = f + 1, t
     # accepted samples: scaled invariants, cyclic sum, Breit-Wigner, product
     m = n_p + 2
-    f += 3 + 4 * n_p + 9 * (n_p * (n_p - 1) // 2) + cycle_sum_flops(m) + 5 + 4 + 1
-    t += 2 + 2 * n_p + n_p * (n_p - 1) // 2 + 1
+    f += 3 + 4 * n_p + 9 * (n_p * (n_p - 1) // 2) + cycle_sum_flops(m) + 5 + 4 + 1 + FLUX
+    t += 2 + 2 * n_p + n_p * (n_p - 1) // 2 + 1 + FLUX_TRANS
     return Census(int(round(f)), int(round(f_fail)), int(t), int(t_fail))
 
 
@@ -109,16 +120,16 @@ def whel(n: int) -> Census:
     D = 3 * n + 5
     f = t = 0
     f += MAP_PER_AXIS * D
-    f += 21  # parton fractions and flux x Jacobian, as for wjets
-    t += 4
+    f += 21 - FLUX  # parton fractions and the Jacobian factor, as for wjets
+    t += 4 - FLUX_TRANS
     for K in range(nf - 2, 0, -1):  # mass chain
         ff, tt = _mass_step(K)
         f += ff + 1
         t += tt + 1
-    f += 17 + (nf - 2) * 52  # two-body steps and boosts
+    f += 13 + (nf - 2) * 34  # two-body steps: boosts and recoils as for wjets
     t += 3 + (nf - 2) * 5
-    f += 8 * (n + 1)  # light-cone components, pT, rapidity of the gluons and the muon
-    t += 4 * (n + 1)
+    f += 10 * (n + 1)  # light-cone components, pT, rapidity, |eta + y_boost| of the gluons and the muon
+    t += 3 * (n + 1)
     if n == 2:
         f += 12  # Durham pT_ij between the two gluons
         t += 3
@@ -136,8 +147,8 @@ def whel(n: int) -> Census:
         f += 3 * (SBAR_U + PROP)  # shared prefixes
         f += 6 * (SBAR + PROP + TOP) + (SBAR_U + PROP + TOP + TOP) + 20 + 10
         t += 2 * 3 + 1 + 9
-    f += 8  # W propagator, prefactor
-    t += 1
+    f += 8 + FLUX  # W propagator, prefactor, flux factor
+    t += 1 + FLUX_TRANS
     return Census(int(round(f)), int(round(f_fail)), int(t), int(t_fail))
 
 

@@ -428,14 +428,16 @@ struct WJetsF {
   // The evaluation in two stages so that a kernel can queue the samples
   // that pass the cuts and run the colour sum on full waves: stage 1 maps
   // x to momenta, applies the cuts and keeps the scaled invariants y_kl of
-  // the coloured set (upper triangle), m_enu^2 - M^2 and the prefactor;
-  // stage 2 forms |M|^2 and f from them.
+  // the coloured set (upper triangle), m_enu^2 - M^2, the prefactor without
+  // the flux and the two logarithms the flux needs; stage 2 forms the flux,
+  // |M|^2 and f from them (the two e^x - 1 run on full waves there).
   static constexpr int NY = MC * (MC - 1) / 2;
   struct State {
     T y[NY];
-    T dm, pref;  // dm = m_enu^2 - M^2; pref = pre s^(n-3) flux Jacobian s^4 / c^m
+    T dm, pref;  // dm = m_enu^2 - M^2; pref = pre s^(n-3) L^2 x0 / sqrt(tau) s^4 / c^m
+    T la, lb;    // ln xa, ln xb: the flux factor is ((1 - xa)(1 - xb))^3
   };
-  static constexpr int kStateWords = NY + 2;
+  static constexpr int kStateWords = NY + 4;
   static constexpr bool kStaged = FULL && sizeof(T) == 4;  // the queue holds FP32
 
   __device__ __forceinline__ static void store_state(const State& st, float* q, int stride, int e) {
@@ -443,6 +445,8 @@ struct WJetsF {
     for (int i = 0; i < NY; ++i) q[i * stride + e] = static_cast<float>(st.y[i]);
     q[NY * stride + e] = static_cast<float>(st.dm);
     q[(NY + 1) * stride + e] = static_cast<float>(st.pref);
+    q[(NY + 2) * stride + e] = static_cast<float>(st.la);
+    q[(NY + 3) * stride + e] = static_cast<float>(st.lb);
   }
   __device__ __forceinline__ static State load_state(const float* q, int stride, int e) {
     State st;
@@ -450,20 +454,21 @@ struct WJetsF {
     for (int i = 0; i < NY; ++i) st.y[i] = static_cast<T>(q[i * stride + e]);
     st.dm = static_cast<T>(q[NY * stride + e]);
     st.pref = static_cast<T>(q[(NY + 1) * stride + e]);
+    st.la = static_cast<T>(q[(NY + 2) * stride + e]);
+    st.lb = static_cast<T>(q[(NY + 3) * stride + e]);
     return st;
   }
 
   // PDF map, phase space and cuts; false when the sample fails the cuts
   __device__ __forceinline__ bool stage1(const T (&x)[D], State& st) const {
-    // parton fractions and flux x Jacobian = L^2 x0 tau^-1/2 ((1-xa)(1-xb))^3
+    // parton fractions and flux x Jacobian = L^2 x0 tau^-1/2 ((1-xa)(1-xb))^3;
+    // the last factor is formed in stage 2
     const T la = L * (T(1) - x[0]);
     const T lb = L * x[0] * (T(1) - x[1]);
     const T ltau = la + lb;
     const T h = vexp2_fast(ltau * T(0.5 * 1.4426950408889634));  // sqrt(tau)
     const T rs = sqrtS * h;           // sqrt(s)
     const T shat = rs * rs;
-    const T om = vexpm1_fast(la) * vexpm1_fast(lb);  // (1 - xa)(1 - xb) without cancellation
-    const T fluxjac = LL * x[0] * (om * om * om) * vrcp(h);
     T spow = T(1);
 #pragma unroll
     for (int i = 0; i < NOUT - 3; ++i) spow *= shat;
@@ -551,7 +556,9 @@ struct WJetsF {
       }
     if constexpr (sizeof(T) == 8) st.dm = fma(Mi[NOUT - 1], Mi[NOUT - 1], -Mv2);
     const T s2 = shat * shat;
-    st.pref = ((pre * spow) * fluxjac) * ldexp_(s2 * s2, -ce * MC);
+    st.pref = ((pre * spow) * (LL * x[0] * vrcp(h))) * ldexp_(s2 * s2, -ce * MC);
+    st.la = la;
+    st.lb = lb;
     return true;
   }
 
@@ -580,7 +587,8 @@ struct WJetsF {
     // ---- Breit-Wigner in m_enu^2 = M_{n-1}^2 (e nu are the last pair)
     const T dm = st.dm;
     const T invD = vrcp(fma(dm, dm, M2G2));
-    const T f = st.pref * (MGpi * invD) * ptsum;
+    const T om = vexpm1_fast(st.la) * vexpm1_fast(st.lb);  // (1 - xa)(1 - xb) without cancellation
+    const T f = (st.pref * (om * om * om)) * (MGpi * invD) * ptsum;
     if (GRAD) {
       g[0] = f * (invM - fma(T(-4) * M, dm, twoMG2) * invD);
       g[1] = f * (invG - T(2) * M * MG * invD);

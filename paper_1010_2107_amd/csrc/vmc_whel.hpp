@@ -190,9 +190,10 @@ struct WHelF {
   // maps x to momenta and applies the cuts; stage 2 forms |M|^2 and f.
   struct State {
     T p[NOUT][4];  // g_1..g_NG, mu+, nu in the partonic frame
-    T Eh, dm, pref, hel;  // sqrt(s)/2, m_munu^2 - M^2, prefactor, helicity configuration
+    T Eh, dm, pref, hel;  // sqrt(s)/2, m_munu^2 - M^2, prefactor without the flux, helicity configuration
+    T la, lb;             // ln xa, ln xb: the flux factor ((1 - xa)(1 - xb))^3 is formed in stage 2
   };
-  static constexpr int kStateWords = 4 * NOUT + 4;
+  static constexpr int kStateWords = 4 * NOUT + 6;
   static constexpr bool kStaged = sizeof(T) == 4;  // the queue holds FP32
 
   __device__ __forceinline__ static void store_state(const State& st, float* q, int stride, int e) {
@@ -204,6 +205,8 @@ struct WHelF {
     q[(4 * NOUT + 1) * stride + e] = static_cast<float>(st.dm);
     q[(4 * NOUT + 2) * stride + e] = static_cast<float>(st.pref);
     q[(4 * NOUT + 3) * stride + e] = static_cast<float>(st.hel);
+    q[(4 * NOUT + 4) * stride + e] = static_cast<float>(st.la);
+    q[(4 * NOUT + 5) * stride + e] = static_cast<float>(st.lb);
   }
   __device__ __forceinline__ static State load_state(const float* q, int stride, int e) {
     State st;
@@ -215,6 +218,8 @@ struct WHelF {
     st.dm = static_cast<T>(q[(4 * NOUT + 1) * stride + e]);
     st.pref = static_cast<T>(q[(4 * NOUT + 2) * stride + e]);
     st.hel = static_cast<T>(q[(4 * NOUT + 3) * stride + e]);
+    st.la = static_cast<T>(q[(4 * NOUT + 4) * stride + e]);
+    st.lb = static_cast<T>(q[(4 * NOUT + 5) * stride + e]);
     return st;
   }
 
@@ -224,8 +229,6 @@ struct WHelF {
     const T h = vexp2_fast((la + lb) * T(0.5 * 1.4426950408889634));  // sqrt(tau)
     const T rs = sqrtS * h;
     const T shat = rs * rs;
-    const T om = vexpm1_fast(la) * vexpm1_fast(lb);
-    const T fluxjac = LL * x[0] * (om * om * om) * vrcp(h);
     const T yb = T(0.5) * (la - lb);
     T Mi[NOUT + 1], Ui[NOUT + 1];
     constexpr bool RES64 = sizeof(T) == 4;
@@ -271,7 +274,9 @@ struct WHelF {
     for (int i = 0; i < NG; ++i) spow *= shat;  // s^(n-3) from V_n / (2 s), s from |A|^2
     st.Eh = T(0.5) * rs;
     if constexpr (sizeof(T) == 8) st.dm = fma(Mi[NOUT - 1], Mi[NOUT - 1], -Mv2);
-    st.pref = (pre * spow) * fluxjac;
+    st.pref = (pre * spow) * (LL * x[0] * vrcp(h));
+    st.la = la;
+    st.lb = lb;
     // the gluon helicity configuration, floor(x 2^NG)
     const int hel = static_cast<int>(x[D - 1] * T(1 << NG));
     st.hel = static_cast<T>(hel < (1 << NG) - 1 ? hel : (1 << NG) - 1);
@@ -366,7 +371,8 @@ struct WHelF {
     // ---- W propagator in m_munu^2 = M_{n-1}^2 (mu nu are the last pair)
     const T dm = st.dm;
     const T invD = vrcp(fma(dm, dm, M2G2));
-    const T f = st.pref * (cs * invD);
+    const T om = vexpm1_fast(st.la) * vexpm1_fast(st.lb);  // (1 - xa)(1 - xb) without cancellation
+    const T f = (st.pref * (om * om * om)) * (cs * invD);
     if (GRAD) {
       g[0] = f * fma(T(4) * M, dm, -twoMG2) * invD;
       g[1] = f * m2M2G * invD;
