@@ -347,6 +347,15 @@ int vmc_iterate_batched(vmc_batch_t b, uint64_t seed, uint32_t it, int kind, uin
  * vmc_refine.  Errors: VMC_E_INVALID, VMC_E_UNBOUND, VMC_E_HIP. */
 int vmc_refine_batched(vmc_batch_t b, double alpha, void *stream);
 
+/* Set the grid of integral k from host memory (d_k axes of nbins + 1
+ * edges, each from 0 to 1 and strictly increasing, in the layout of that
+ * integral's part of out[0]) and rebuild its FP32 table, as vmc_set_edges
+ * does for one grid (Sec. 2: the grid the next iteration samples).  Copies
+ * synchronously; advances the grid-state version.  Errors: VMC_E_UNBOUND,
+ * VMC_E_INVALID (k out of range, NULL), VMC_E_GRID (edges not a grid),
+ * VMC_E_HIP. */
+int vmc_batch_set_edges(vmc_batch_t b, int k, const double *host_edges, void *stream);
+
 /* Clear every integral's running combination (BASES integration phase). */
 int vmc_batch_combine_reset(vmc_batch_t b, void *stream);
 

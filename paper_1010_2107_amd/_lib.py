@@ -80,6 +80,7 @@ _SIGS = {
     "vmc_iterate_batched": (_c.c_int, [_vp, _c.c_uint64, _c.c_uint32, _c.c_int, _c.c_uint32, _vp]),
     "vmc_refine_batched": (_c.c_int, [_vp, _c.c_double, _vp]),
     "vmc_batch_combine_reset": (_c.c_int, [_vp, _vp]),
+    "vmc_batch_set_edges": (_c.c_int, [_vp, _c.c_int, _vp, _vp]),
     "vmc_batch_timing": (_c.c_int, [_vp, _c.c_int, _c.POINTER(_c.c_double), _c.POINTER(_c.c_int64)]),
     "vmc_probe_lds_atomics": (_c.c_int, [_c.c_int, _c.c_int, _c.POINTER(_c.c_double), _vp]),
     "vmc_probe_fp32_fma": (_c.c_int, [_c.c_int, _c.c_int, _c.POINTER(_c.c_double), _vp]),

@@ -76,6 +76,12 @@ class Batch:
     def refine(self, alpha=1.5, stream=None):
         L.call("vmc_refine_batched", self._h, float(alpha), _stream_ptr(stream))
 
+    def set_edges(self, k, edges, stream=None):
+        """Grid of integral k from host memory ([d_k][nbins + 1] doubles)."""
+        e = np.ascontiguousarray(edges, dtype=np.float64)
+        assert e.shape == (int(self.dims[k]), self.nbins + 1), e.shape
+        L.call("vmc_batch_set_edges", self._h, int(k), e.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream))
+
     def combine_reset(self, stream=None):
         L.call("vmc_batch_combine_reset", self._h, _stream_ptr(stream))
 

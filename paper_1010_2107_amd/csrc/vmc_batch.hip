@@ -574,6 +574,32 @@ int vmc_refine_batched(vmc_batch_t b, double alpha, void* stream) {
   return VMC_OK;
 }
 
+int vmc_batch_set_edges(vmc_batch_t b, int k, const double* host_edges, void* stream) {
+  int rc = need_bound(b);
+  if (rc) return rc;
+  if (k < 0 || k >= b->n) return fail(VMC_E_INVALID, "integral %d outside [0, %d)", k, b->n);
+  if (!host_edges) return fail(VMC_E_INVALID, "host_edges is NULL");
+  const BatchDesc& ds = b->desc[k];
+  const int d = static_cast<int>(ds.d), N = b->N;
+  for (int a = 0; a < d; ++a) {
+    const double* e = host_edges + static_cast<size_t>(a) * (N + 1);
+    if (e[0] != 0.0 || e[N] != 1.0)
+      return fail(VMC_E_GRID, "integral %d axis %d: edges must run from 0 to 1 (got %g .. %g)", k, a, e[0], e[N]);
+    for (int j = 0; j < N; ++j)
+      if (!(e[j + 1] > e[j]))
+        return fail(VMC_E_GRID, "integral %d axis %d: edges not strictly increasing at bin %d", k, a, j);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ++b->version;
+  HIP_TRY(hipMemcpyAsync(b->edges + ds.off_edges, host_edges, sizeof(double) * d * (N + 1), hipMemcpyHostToDevice, st),
+          "edges H2D");
+  hipLaunchKernelGGL(k_table, dim3((d * N + kBlock - 1) / kBlock), dim3(kBlock), 0, st, b->edges + ds.off_edges,
+                     b->table + ds.off_table, d, N);
+  HIP_TRY(hipGetLastError(), "k_table launch");
+  HIP_TRY(hipStreamSynchronize(st), "stream synchronize");
+  return VMC_OK;
+}
+
 int vmc_batch_combine_reset(vmc_batch_t b, void* stream) {
   int rc = need_bound(b);
   if (rc) return rc;

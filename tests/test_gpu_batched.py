@@ -1,8 +1,10 @@
 """GPU parity of the batched persistent launch: each integral of a batch
 against the FP64 oracle with integral id k (Philox counter word 3 = k).
 Tolerances as for one grid: 1e-12 for the FP64 instantiation, 1e-5 relative
-(norm-wise for bins) for the FP32 integrand; schedules agree to FP64
-summation order (1e-12); the batched configuration meets its closed forms."""
+(norm-wise for bins) for the FP32 integrand; after each refinement both
+sides continue from the oracle's grid (vmc_batch_set_edges); schedules
+agree to FP64 summation order (1e-12); the batched configuration meets its
+closed forms."""
 import math
 
 import numpy as np
@@ -56,9 +58,12 @@ def test_batched_matches_oracle_per_integral(fp64, nbins):
         b.refine(1.5)
         for k in range(len(DIMS)):
             ref = O.iterate(W.GAUSS_AXES, edges[k], th[k], NCALLS[k], 1234, it, kid=k)
-            new = O.refine(edges[k], ref["bins"][1], 1.5) if fp64 else b.edges_of(k)
+            new = O.refine(edges[k], ref["bins"][1], 1.5)
             if fp64:
                 assert np.max(np.abs(b.edges_of(k) - new)) <= 1e-12
+            # both sides go on from the oracle's grid: edges that differ by
+            # rounding would move steep integrands' weights by more than 1e-12
+            b.set_edges(k, new)
             edges[k] = new
 
 

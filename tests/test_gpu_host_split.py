@@ -3,9 +3,10 @@ library dumps each sample's FP32 weight and bin indices, the host
 accumulates and refines (the bench's ablation leg).  Bin indices equal the
 oracle's bit for bit; host sums against the oracle at the same FP32 point
 (S1 and plane 0 1e-5, S2 and plane 1 2e-5) and against the oracle's replay
-of the dumped weights (1e-12); host refinement against the oracle's on the
-host sums (1e-12); and two host-split iterations against the GPU-resident
-pass on the same grid (same FP32 weights, so 1e-12)."""
+of the dumped weights (1e-12); the host refinement against the oracle's on
+the oracle's sums (1e-12); and two host-split iterations against the
+GPU-resident pass and its refinement on the same grid (same FP32 weights,
+so 1e-12)."""
 import numpy as np
 import pytest
 import torch
@@ -44,13 +45,15 @@ def test_host_split_matches_oracle_and_gpu_resident_pass():
             rep = O.iterate(w.integrand, edges, w.theta, ncall, w.seed, it, w_in=wh)
             assert rel(S1, rep["S1"]) <= 1e-12 and rel(S2, rep["S2"]) <= 1e-12
             assert normwise(bins, rep["bins"]) <= 1e-12
+            # the host refinement is the oracle's on the oracle's own sums
+            assert np.max(np.abs(bench.host_refine(edges, o32["bins"][1], w.alpha) -
+                                 O.refine(edges, o32["bins"][1], w.alpha))) <= 1e-12
         # the GPU-resident pass on the same grid adds the same FP32 weights
         ref_grid.iterate(w.integrand, w.theta, ncall, w.seed, it)
         r = ref_grid.result()
         assert rel(S1, r["S1"]) <= 1e-12 and rel(S2, r["S2"]) <= 1e-12
         assert normwise(bins, ref_grid.bins.cpu().numpy()) <= 1e-12
         new = bench.host_refine(edges, bins[1], w.alpha)
-        assert np.max(np.abs(new - O.refine(edges, bins[1], w.alpha))) <= 1e-12
         ref_grid.refine(w.alpha)
         assert np.max(np.abs(new - ref_grid.get_edges())) <= 1e-12
         edges = new
