@@ -115,6 +115,59 @@ def run_loop(grid, w, steps, adjoint=False, fused=False):
     return t0.elapsed_time(t1), kms, nl
 
 
+def record_loop(grid, w, steps, adjoint=False, fused=False):
+    """The loop of run_loop (reset, `steps` iterations with their refinement
+    and the BASES phase switch) recorded once as a HIP graph, so that a
+    replay launches the whole loop at once instead of three or four kernels
+    per iteration from the host.  An eager run on a side stream first sets
+    up the library's per-device state.  Returns the torch.cuda.CUDAGraph."""
+    import torch
+    th = grid.theta_tensor(w.theta)
+
+    def issue():
+        grid.reset()
+        grid.stratify(w.ng)
+        for it in range(steps):
+            if fused:
+                grid.fused(w.integrand, th, w.ncall, w.seed, it)
+            else:
+                grid.iterate(w.integrand, th, w.ncall, w.seed, it)
+                if adjoint:
+                    grid.adjoint(w.integrand, th, w.ncall, w.seed, it)
+            if it < w.itmx:
+                grid.refine(w.alpha)
+            if w.itmx2 and it + 1 == w.itmx:
+                grid.combine_reset()
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        issue()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        issue()
+    return graph
+
+
+def median_replay(graph, repeats):
+    """Median wall time (ms, HIP events on the replay stream) of `repeats`
+    replays of a recorded loop, with every time."""
+    import torch
+    times = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        graph.replay()
+        t1.record()
+        torch.cuda.synchronize()
+        times.append(t0.elapsed_time(t1))
+    return sorted(times)[len(times) // 2], times
+
+
 def cpu_baseline(w, edges, budget_s=15.0):
     """The FP64 oracle, single thread, on a bounded sample of the workload:
     a short probe sets the sample count so that one oracle iteration on the
@@ -177,19 +230,29 @@ def median_loop(grid, w, steps, repeats, **kw):
 
 def measure_workload(grid, w, steps, warmup, repeats=5):
     """Forward loop (value), forward + separate adjoint, and fused loops,
-    each the median of `repeats` timed loops."""
+    each the median of `repeats` replays of the loop recorded as a HIP
+    graph; beside them the same loops launched call by call from the host
+    (eager), whose per-launch kernel times feed the roofline."""
     from paper_1010_2107_amd import workloads as W
     if warmup:
         run_loop(grid, w, warmup)
-    (ms, kms, nl), all_ms = median_loop(grid, w, steps, repeats)
+    (ems, kms, nl), eager_ms = median_loop(grid, w, steps, repeats)
+    eres = grid.result()
+    ms, all_ms = median_replay(record_loop(grid, w, steps), repeats)
     res = grid.result()
-    out = dict(ms=ms, kms=kms, nl=nl, res=res, n_eff=res["n_eff"], value=res["n_eff"] * steps / (ms / 1e3),
-               repeats_ms=all_ms)
+    n = res["n_eff"] * steps
+    out = dict(ms=ms, kms=kms, nl=nl, res=res, n_eff=res["n_eff"], value=n / (ms / 1e3), repeats_ms=all_ms,
+               eager_value=eres["n_eff"] * steps / (ems / 1e3), eager_repeats_ms=eager_ms,
+               graph_matches_eager=bool(abs(res["Ibar"] - eres["Ibar"]) <= 1e-9 * abs(eres["Ibar"])))
     if W.ngrad(w) > 0:
-        (ms_a, _, _), _ = median_loop(grid, w, steps, repeats, adjoint=True)
-        (ms_f, _, _), _ = median_loop(grid, w, steps, repeats, fused=True)
-        out["fwd_adj_evals_per_s"] = res["n_eff"] * steps / (ms_a / 1e3)
-        out["fused_evals_per_s"] = res["n_eff"] * steps / (ms_f / 1e3)
+        ms_a, _ = median_replay(record_loop(grid, w, steps, adjoint=True), repeats)
+        ms_f, _ = median_replay(record_loop(grid, w, steps, fused=True), repeats)
+        (ems_a, _, _), _ = median_loop(grid, w, steps, repeats, adjoint=True)
+        (ems_f, _, _), _ = median_loop(grid, w, steps, repeats, fused=True)
+        out["fwd_adj_evals_per_s"] = n / (ms_a / 1e3)
+        out["fused_evals_per_s"] = n / (ms_f / 1e3)
+        out["eager_fwd_adj_evals_per_s"] = n / (ems_a / 1e3)
+        out["eager_fused_evals_per_s"] = n / (ems_f / 1e3)
     return out
 
 
@@ -358,7 +421,9 @@ PAPER_GTX285_CALLS_PER_S = {0: {"vegas": 1 / 0.0207e-6, "bases": 1 / 0.0260e-6},
 def paper_process_leg():
     """The paper's process at the paper's run sizes (Table 5: NCALL 1e6,
     ITMX 10 for VEGAS, ITMX1 = ITMX2 = 5 for BASES), helicity amplitudes in
-    FP32, whole iteration loop timed (sample pass, publish, refine)."""
+    FP32, whole iteration loop timed (sample pass, publish, refine): the
+    median of 5 replays of the loop recorded as a HIP graph, and of 5 eager
+    loops."""
     import torch
 
     from paper_1010_2107_amd import workloads as W
@@ -374,10 +439,12 @@ def paper_process_leg():
             g = Grid(d, 64)
             steps = w.itmx + w.itmx2
             run_loop(g, w, steps)  # warm-up
-            ms, kms, nl = run_loop(g, w, steps)
+            (ems, kms, nl), _ = median_loop(g, w, steps, 5)
+            ms, _ = median_replay(record_loop(g, w, steps), 5)
             r = g.result()
             rate = r["n_eff"] * steps / (ms / 1e3)
-            out[w.name] = {"calls_per_s": rate, "kernel_ms_per_launch": kms / max(nl, 1), "Ibar": r["Ibar"],
+            out[w.name] = {"calls_per_s": rate, "eager_calls_per_s": r["n_eff"] * steps / (ems / 1e3),
+                           "kernel_ms_per_launch": kms / max(nl, 1), "Ibar": r["Ibar"],
                            "sigbar": r["sigbar"], "paper_gtx285_calls_per_s": PAPER_GTX285_CALLS_PER_S[n][mode]}
     return out
 
@@ -585,7 +652,10 @@ def main(argv=None):
     line = {
         "metric": "integrand evals/s (fwd)", "value": m["value"], "unit": "evals/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": m["ms"] / steps, "repeats": len(m["repeats_ms"]),
-        "loop_ms_of_repeats": m["repeats_ms"], "higher_is_better": True, "scaling": "weak",
+        "loop_ms_of_repeats": m["repeats_ms"],
+        "loop": "the K-step loop recorded once as a HIP graph and replayed (median of the repeats)",
+        "eager_evals_per_s": m["eager_value"], "eager_loop_ms_of_repeats": m["eager_repeats_ms"],
+        "graph_matches_eager": m["graph_matches_eager"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32 integrand, f64 sums", "data": "synthetic (counter-based Philox samples)",
         "config": {"workload": w.name, "dim": w.dim, "nbins": w.nbins, "ncall": w.ncall, "n_eff": n_eff,
                    "iterations": steps, "mode": "bases-stratified" if w.ng > 1 else "vegas",
@@ -595,7 +665,7 @@ def main(argv=None):
                    "within_3_sigma": None if z is None else bool(z < 3)},
         "roofline": roof,
     }
-    for key in ("fwd_adj_evals_per_s", "fused_evals_per_s"):
+    for key in ("fwd_adj_evals_per_s", "fused_evals_per_s", "eager_fwd_adj_evals_per_s", "eager_fused_evals_per_s"):
         if key in m:
             line[key] = m[key]
     if not args.no_secondary:
@@ -613,7 +683,8 @@ def main(argv=None):
                 ref = json.load(open(p)).get(str(w2.dim)) if os.path.exists(p) else None
                 if ref:
                     z2 = abs(r2["Ibar"] - ref["Ibar"]) / math.hypot(r2["sigbar"], ref["sigbar"])
-            sec[w2.name] = {k: m2[k] for k in ("value", "fwd_adj_evals_per_s", "fused_evals_per_s") if k in m2}
+            sec[w2.name] = {k: m2[k] for k in ("value", "eager_value", "fwd_adj_evals_per_s", "fused_evals_per_s",
+                                               "graph_matches_eager") if k in m2}
             sec[w2.name].update({"Ibar": r2["Ibar"], "sigbar": r2["sigbar"], "z": z2,
                                  "kernel_ms_per_launch": m2["kms"] / max(m2["nl"], 1)})
             print(f"[bench] {w2.name}: {m2['value']:.4g} evals/s", file=sys.stderr, flush=True)

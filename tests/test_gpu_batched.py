@@ -113,3 +113,41 @@ def test_batched_configuration_closed_forms():
         gzmax = max(gzmax, gz.max())
     print(f"max |z| integrals {zmax:.2f}, gradients (last iteration) {gzmax:.2f}")
     assert zmax < 4.5 and gzmax < 4.5
+
+
+def test_batched_set_edges():
+    """A grid set from the host is the grid the integral samples (its FP32
+    table rebuilt: the next iteration equals the oracle's on those edges),
+    and malformed calls are refused without touching the grids."""
+    import ctypes
+
+    from paper_1010_2107_amd import _lib as L
+    from paper_1010_2107_amd._lib import VmcError
+    announce("batched set_edges")
+    dims, ncalls = [3, 5], [20_001, 30_003]
+    th = _thetas(dims, 9)
+    b = Batch(dims, ncalls, th, nbins=32)
+    rng = np.random.default_rng(11)
+    edges = []
+    for d in dims:
+        w = rng.gamma(2.0, size=(d, 32)) + 0.05
+        e = np.concatenate([np.zeros((d, 1)), np.cumsum(w, axis=1)], axis=1)
+        e /= e[:, -1:]
+        e[:, -1] = 1.0
+        edges.append(e)
+        b.set_edges(len(edges) - 1, e)
+    for k in range(len(dims)):
+        assert np.array_equal(b.edges_of(k), edges[k])
+    b.iterate(5, 1, kind=1, fp64=True)
+    r = b.results()
+    for k, d in enumerate(dims):
+        ref = O.iterate(W.GAUSS_AXES, edges[k], th[k], ncalls[k], 5, 1, kid=k)
+        assert rel(r["S1"][k], ref["S1"]) <= 1e-12 and normwise(b.bins_of(k), ref["bins"]) <= 1e-12
+    bad = edges[0].copy()
+    bad[1, 5] = bad[1, 4]  # not strictly increasing
+    for k, e, name in ((2, edges[0], "VMC_E_INVALID"), (-1, edges[0], "VMC_E_INVALID"), (0, bad, "VMC_E_GRID")):
+        with pytest.raises(VmcError) as ex:
+            # through the C ABI: the binding's shape check would stop k out of range first
+            L.call("vmc_batch_set_edges", b._h, k, e.ctypes.data_as(ctypes.c_void_p), None)
+        assert ex.value.name == name
+    assert np.array_equal(b.edges_of(0), edges[0])
