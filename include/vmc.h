@@ -263,7 +263,9 @@ int vmc_dump_samples(vmc_grid_t g, int integrand, const double *theta, int nthet
 /* Launch shape of the sample kernels: one tile per thread block.
  * block_samples: samples (plain) or cube units (stratified) per tile, a
  * multiple of 256 in [256, 2^24], or 0 for the built-in choice (plain: at
- * least 1024 tiles of at most 8192 samples; stratified: 256 units, one
+ * least 1024 tiles of at most 8192 samples, and for the W + partons and
+ * helicity integrands at least two tiles per block the device holds at
+ * once unless that takes tiles below 1024 samples; stratified: 256 units, one
  * per thread, or up to 1024 when a unit holds few samples, toward 4096
  * samples per tile, but at least about 512 tiles);
  * chunks_per_cube: lanes that share one cube in stratified mode, a power of

@@ -391,6 +391,18 @@ int launch_sample(vmc_grid_t g, Plan& P, int kind, hipStream_t stream, bool stat
     b = ((b + kBlock - 1) / kBlock) * kBlock;
     b = std::max<uint64_t>(b, kBlock);
     if (!P.strat) b = std::min<uint64_t>(b, 8192);
+    if (!P.strat && P.ks->queue_bytes) {
+      // queued integrands (cut-dependent cost per tile): at least two tiles
+      // per block the device holds at once, so that the dispatcher can even
+      // out slow tiles, but tiles of at least 1024 samples
+      int resident = 0;
+      int rc = resident_blocks(fn, lds, &resident);
+      if (rc) return rc;
+      const uint64_t want = 2 * static_cast<uint64_t>(resident);
+      uint64_t br = (P.items + want - 1) / want;
+      br = ((br + kBlock - 1) / kBlock) * kBlock;
+      b = std::min<uint64_t>(b, std::max<uint64_t>(br, 1024));
+    }
     A.block_items = b;
   }
   A.ntiles = (P.items + A.block_items - 1) / A.block_items;
