@@ -64,17 +64,20 @@ MASS_START_DEG = 5  # degree of the fitted start polynomial (csrc/vmc_mass_start
 
 
 def _mass_step(K):
-    """Flops and transcendentals of one mass-fraction solve.  K = 1 is in
-    closed form.  Otherwise: the start on the lane's side (two scalings and
-    log2/exp2, or 1 - r, a scaling and a square root), the correction
-    polynomial and its product with s, one Newton step on v^2 H(v) - target
-    (H and H' by Horner, the residual, the derivative, a reciprocal and the
-    update), and 1 - v."""
+    """FP32 flops and transcendentals of one mass-fraction solve in the FP32
+    kernels.  K = 1 is in closed form (1 - r, 1 + s, the product, and the
+    scaling of the Newton step's reciprocal; the step itself is FP64).
+    Otherwise: the start on the lane's side (1 - r and a scaling, then
+    square roots for K = 2 and 4, log2, a scaling and exp2 for K = 3), the
+    correction polynomial and its product with s, and the FP32 derivative of
+    the Newton step, K (K+1) t^(K-1) (1 - t) (1 - v, K - 1 products and one
+    more); the residual, the update and 1 - v are FP64 and not counted."""
     if K == 1:
-        return 3, 2
-    start = 2.5 + 2 * MASS_START_DEG + 1
-    step = 2 * (K - 1) + 2 * (K - 2) + 1 + 2 + 1 + 2 + 1 + 1 + 1
-    return start + step + 1, 1.5 + 1
+        return 4, 3
+    start = 2 + 2 * MASS_START_DEG + 1 + (1 if K == 3 else 0)
+    deriv = 1 + (K - 1) + 1
+    trans = {2: 1, 3: 2, 4: 1.5}.get(K, 2) + 1  # the start's roots or log2/exp2, and the reciprocal
+    return start + deriv, trans
 
 
 def wjets(n_p: int) -> Census:

@@ -171,9 +171,19 @@ __device__ __forceinline__ TU<T> mass_fraction(T r) {
     constexpr int row = K - kMassStartMinK;
     const bool lo = r < T(0.5);
     const T q = T(1) - r;  // exact for r >= 1/2
-    // s = (r / (K+1))^(1/K) or (2 q / (K (K+1)))^(1/2), one log2 and one exp2
+    // s = (r / (K+1))^(1/K) or (2 q / (K (K+1)))^(1/2): square roots where
+    // both sides' powers are roots of two, else one log2 and one exp2
+    // (a = 0 gives log2 = -inf and s = 0)
     const T a = lo ? r * T(1.0 / (K + 1)) : q * T(2.0 / (K * (K + 1)));
-    const T s = a > T(0) ? vexp2_fast(vlog2_fast(a) * (lo ? T(1.0 / K) : T(0.5))) : T(0);
+    T s;
+    if constexpr (K == 2) {
+      s = vsqrt(a);
+    } else if constexpr (K == 4) {
+      const T sa = vsqrt(a);
+      s = lo ? vsqrt(sa) : sa;
+    } else {
+      s = vexp2_fast(vlog2_fast(a) * (lo ? T(1.0 / K) : T(0.5)));
+    }
     T rl = T(kMassStartLo[row][kMassStartDeg]), rh = T(kMassStartHi[row][kMassStartDeg]);
 #pragma unroll
     for (int j = kMassStartDeg - 1; j >= 0; --j) {
@@ -183,18 +193,20 @@ __device__ __forceinline__ TU<T> mass_fraction(T r) {
     T v = fmin(s * (lo ? rl : rh), T(1));
     const T target = lo ? r : q;
     if constexpr (F32) {
-      // residual in FP64, derivative in FP32 (its Horner running on the
-      // FP64 partial values rounded to FP32)
+      // residual in FP64; its derivative in FP32 from the closed form: on
+      // both sides dR/dv = F'(t) = K (K+1) t^(K-1) (1 - t) with t = v (low)
+      // or 1 - v (high)
       const double vd = static_cast<double>(v);
       double H = lo ? low_coef<K>(K - 1) : comp_coef<K>(K + 1);
-      T Hd = T(0);
 #pragma unroll
-      for (int j = K - 2; j >= 0; --j) {
-        Hd = fma(Hd, v, static_cast<T>(H));
-        H = fma(H, vd, lo ? low_coef<K>(j) : comp_coef<K>(j + 2));
-      }
+      for (int j = K - 2; j >= 0; --j) H = fma(H, vd, lo ? low_coef<K>(j) : comp_coef<K>(j + 2));
       const double res = fma(vd * vd, H, -static_cast<double>(target));
-      const T dP = v * fma(v, Hd, T(2) * static_cast<T>(H));  // > 0 inside (0, 1]; 0 at v = 0 where res = 0
+      const T om = T(1) - v;
+      const T tt = lo ? v : om, uu = lo ? om : v;
+      T tp = T(K * (K + 1));
+#pragma unroll
+      for (int j = 0; j < K - 1; ++j) tp *= tt;
+      const T dP = tp * uu;  // > 0 inside (0, 1); 0 at v = 0 where res = 0
       double v64 = vd - res * static_cast<double>(vrcp(fmax(dP, T(1e-30))));
       v64 = fmin(fmax(v64, 0.0), 1.0);
       const double t64 = lo ? v64 : 1.0 - v64;
