@@ -250,7 +250,7 @@ struct WHelF {
       pt[j] = lc.pt;
       pt2[j] = lc.pt2;
       eta[j] = lc.eta;
-      pass = pass && (lc.pt2 > ptmin2) && (fabs(lc.eta + yb) < (j < NG ? eta_g : eta_mu));
+      pass = pass & (lc.pt2 > ptmin2) & (fabs(lc.eta + yb) < (j < NG ? eta_g : eta_mu));
     }
     if constexpr (NG == 2) {
       // min(pT_i, pT_j)^2 (Delta eta^2 + Delta phi^2) > pTij^2: with
@@ -266,7 +266,7 @@ struct WHelF {
         T sz;
         vsincos2pi(vsqrt(fmax(z, T(0))) * T(0.15915494309189535), sz, cz);
       }
-      pass = pass && ((z <= T(0)) || (z < T(9.869604401089358) && dot < cz * pt[0] * pt[1]));
+      pass = pass & ((z <= T(0)) | ((z < T(9.869604401089358)) & (dot < cz * pt[0] * pt[1])));
     }
     if (!pass) return false;
     T spow = T(1);
