@@ -148,7 +148,11 @@ def whel(n: int) -> Census:
     else:
         f += 2 * 15 + 60  # polarisations, three-gluon current
         f += 3 * (SBAR_U + PROP)  # shared prefixes
-        f += 6 * (SBAR + PROP + TOP) + (SBAR_U + PROP + TOP + TOP) + 20 + 10
+        # the two colour orders: four chains each ending in its own vertex
+        # and propagator, the chains sharing both summed before them (four
+        # spinor additions), the three-gluon terms (one sbar_u, one top),
+        # the complex sums and the colour matrix
+        f += 6 * SBAR + 4 * (PROP + TOP) + (SBAR_U + TOP) + 4 * 4 + 8 + 10
         t += 2 * 3 + 1 + 9
     f += 8 + FLUX  # W propagator, prefactor, flux factor
     t += 1 + FLUX_TRANS

@@ -55,6 +55,14 @@ template <typename T>
 struct Sp {  // a 2-component spinor
   Cx<T> a, b;
 };
+template <typename T>
+__device__ __forceinline__ Sp<T> operator+(const Sp<T>& x, const Sp<T>& y) {
+  return {x.a + y.a, x.b + y.b};
+}
+template <typename T>
+__device__ __forceinline__ Sp<T> operator-(const Sp<T>& x, const Sp<T>& y) {
+  return {x.a - y.a, x.b - y.b};
+}
 // A complex four-vector V held as its 2x2 block V.sigmabar =
 // [[p, lo], [hi, m]] with p = V0 + V3, m = V0 - V3, lo = V1 - i V2,
 // hi = V1 + i V2: the light-cone components are formed directly from
@@ -359,12 +367,16 @@ struct WHelF {
         const Sp<T> ya = prop(Pk2, sbar_u(e2.b));  // gluon 2 first
         const Sp<T> yw = prop(Pk1, sbar_u(e1.b));  // gluon 1 first
         const Sp<T> yc = prop(Pq, uL);             // W first
-        // colour T^a1 T^a2 (gluon 1 nearer the dbar end) and T^a2 T^a1
-        const Cx<T> Tt = sbar_top(Lc, prop(PK, sbar_u(J))) + sbar_top(J, yc);
-        const Cx<T> A12 = sbar_top(Lc, prop(PK, sbar(e1.b, ya))) + sbar_top(e1.b, prop(Pk2q, sbar(Lc, ya))) +
-                          sbar_top(e1.b, prop(Pk2q, sbar(e2.b, yc))) + Tt;
-        const Cx<T> A21 = sbar_top(Lc, prop(PK, sbar(e2.b, yw))) + sbar_top(e2.b, prop(Pk1q, sbar(Lc, yw))) +
-                          sbar_top(e2.b, prop(Pk1q, sbar(e1.b, yc))) - Tt;
+        // colour T^a1 T^a2 (gluon 1 nearer the dbar end) and T^a2 T^a1; the
+        // three-gluon diagrams enter the two with opposite signs.  Chains
+        // that end in the same vertex and propagator are summed before them
+        // (both are linear maps of the spinor they act on).
+        const Sp<T> uJ = sbar_u(J);
+        const Cx<T> tJ = sbar_top(J, yc);
+        const Cx<T> A12 = sbar_top(Lc, prop(PK, sbar(e1.b, ya) + uJ)) +
+                          sbar_top(e1.b, prop(Pk2q, sbar(Lc, ya) + sbar(e2.b, yc))) + tJ;
+        const Cx<T> A21 = sbar_top(Lc, prop(PK, sbar(e2.b, yw) - uJ)) +
+                          sbar_top(e2.b, prop(Pk1q, sbar(Lc, yw) + sbar(e1.b, yc))) - tJ;
         cs = T(16.0 / 3.0) * (norm2(A12) + norm2(A21)) - T(4.0 / 3.0) * fma(A12.r, A21.r, A12.i * A21.i);
       }
     }
