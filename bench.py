@@ -670,7 +670,7 @@ def main(argv=None):
             line[key] = m[key]
     if not args.no_secondary:
         sec = {}
-        for w2 in (W.C2, W.C2_PLAIN, W.C3, W.C6):
+        for w2 in (W.C2, W.C2_PLAIN, W.C3, W.C6, W.C3_BASES, W.C4_BASES):
             if w2.name == w.name:
                 continue
             g2 = Grid(w2.dim, w2.nbins)

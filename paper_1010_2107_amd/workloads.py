@@ -54,10 +54,14 @@ C2 = Workload("dgauss_d8_bases", DGAUSS, 8, 128, 5_000_000, 10, (1 / 3, 2 / 3, 0
 C2_PLAIN = replace(C2, name="dgauss_d8_vegas", ng=1, itmx=20, itmx2=0)
 C3 = Workload("wjets2_d10_vegas", WJETS, 10, 64, 10_000_000, 15, WJETS_THETA)
 C4 = Workload("wjets4_d16_vegas", WJETS, 16, 64, 50_000_000, 20, WJETS_THETA)
+# the BASES forms of the two: ng^d cubes of k samples (4^10 x 9 and 2^16 x
+# 762, about the plain forms' calls), ITMX1 + ITMX2 = the plain ITMX
+C3_BASES = replace(C3, name="wjets2_d10_bases", ncall=4**10 * 9, ng=4, itmx=8, itmx2=7)
+C4_BASES = replace(C4, name="wjets4_d16_bases", ncall=2**16 * 762, ng=2, itmx=10, itmx2=10)
 # u dbar -> W+(-> mu+ nu) + 2 gluons from helicity amplitudes, d = 11
 C6 = Workload("whel2_d11_vegas", WHEL, 11, 64, 10_000_000, 15, WHEL_THETA)
 
-CONFIGS = {w.name: w for w in (C1, C2, C2_PLAIN, C3, C4, C6)}
+CONFIGS = {w.name: w for w in (C1, C2, C2_PLAIN, C3, C4, C3_BASES, C4_BASES, C6)}
 DEFAULT_BENCH = C4
 
 
