@@ -610,15 +610,27 @@ def main(argv=None):
                 z = abs(res["Ibar"] - ref["Ibar"]) / math.hypot(res["sigbar"], ref["sigbar"])
                 ref_note = {"I_ref": ref["Ibar"], "sig_ref": ref["sigbar"], "source": "FP64 oracle, independent seed"}
 
+    # achieved: the algorithm's operation count per sample (census.ALGORITHMIC)
+    # x samples per launch / average launch; beside it the same for the
+    # FP32 operations the kernel's source executes (census.for_workload)
     cen = census.for_workload(w)
     frac_pass = 1.0 - res["n_zero"] / max(n_eff, 1)
-    flops = cen.flops(frac_pass)
+    executed = cen.flops(frac_pass)
+    alg = census.algorithmic_flops(w, frac_pass)
+    flops = alg if alg is not None else executed
     avg_ms = m["kms"] / max(m["nl"], 1)
     achieved = flops * n_eff / (avg_ms / 1e3) / 1e12
+    ex_achieved = executed * n_eff / (avg_ms / 1e3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": measured_traffic(w.name),
             "kernel": "sample-and-accumulate (forward)", "avg_launch_ms": avg_ms, "launches": m["nl"],
-            "flops_per_sample": flops, "accepted_fraction": frac_pass, "samples_per_launch": n_eff}
+            "flops_per_sample": flops,
+            "flops_basis": "the algorithm's operation count per sample" if alg is not None
+            else "the FP32 operations the kernel source executes per sample",
+            "accepted_fraction": frac_pass, "samples_per_launch": n_eff,
+            "executed": {"flops_per_sample": executed, "achieved": ex_achieved,
+                         "frac": ex_achieved / PEAK_FP32_TFLOPS,
+                         "note": "FP32 operations of the kernel source (the arithmetic it actually does)"}}
     # the kernel against the rates probe kernels measure on this chip: FP32 FMA
     # issue (packed FP32 off, at the clock held under load) and LDS FP64 adds
     from paper_1010_2107_amd import _lib as L
@@ -627,6 +639,7 @@ def main(argv=None):
     fma = ctypes.c_double()
     L.call("vmc_probe_fp32_fma", 8192, 4096, ctypes.byref(fma), stream)
     roof["fp32_fma_probe"] = {"peak_tflops": fma.value / 1e12, "frac": achieved / (fma.value / 1e12),
+                              "executed_frac": ex_achieved / (fma.value / 1e12),
                               "note": "8 independent FP32 FMA chains per lane, packed FP32 off"}
     # VALU issue estimate: the counted VALU wave instructions at the FMA
     # probe's issue rate (one wave FMA = 2 x 64 flops per 4 cycles per SIMD).

@@ -171,6 +171,34 @@ def gaussian(integrand: int, d: int) -> Census:
     return Census(fl, fl, tr, tr)
 
 
+# The algorithm's FP32 operation count per sample, step by step as the
+# method states the work rather than as the kernel arranges it: the colour
+# sum with every cyclic order written out (60 orders of six objects for
+# four partons), each invariant as a Minkowski product, RAMBO on diet with
+# both momenta boosted at every two-body step, the cuts, the grid map
+# (3 per axis).  Per-step estimates for the workloads the measurement
+# quotes; the colour sum, the invariants and the Breit-Wigner factor run on
+# accepted samples only.  (integrand, dim) -> (always, accepted only).
+ALGORITHMIC = {
+    # phase space 320, cuts 185, map 48, rest 50 | colour sum 420, invariants 105
+    (W.WJETS, 16): (320 + 185 + 48 + 50, 420 + 105),
+    # map 30, parton fractions and flux 20, phase space 125, cuts 95, rest 20 |
+    # colour sum, invariants and Breit-Wigner 50
+    (W.WJETS, 10): (30 + 20 + 125 + 95 + 20, 50),
+    (W.DGAUSS, 8): (110, 0),
+    (W.GAUSS, 4): (45, 0),
+}
+
+
+def algorithmic_flops(w, accepted_fraction: float) -> float | None:
+    """The algorithm's FP32 flops per sample of a workload (ALGORITHMIC), or
+    None where no such count is set (then the executed census applies)."""
+    c = ALGORITHMIC.get((w.integrand, w.dim))
+    if c is None:
+        return None
+    return c[0] + accepted_fraction * c[1]
+
+
 def for_workload(w) -> Census:
     if w.integrand == W.WJETS:
         return wjets((w.dim - 4) // 3)
