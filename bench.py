@@ -221,6 +221,35 @@ def cpu_baseline_all_cores(w, edges, ncall):
                        f"processes ({res['seconds']:.1f} s)")
 
 
+def autograd_loop(grid, w, steps):
+    """`steps` iterations through torch.autograd: the forward pass
+    (vegas_integral) and backward() on the differentiable parameters, then
+    the refinement; returns the wall time in ms (HIP events)."""
+    import torch
+
+    from paper_1010_2107_amd import _lib as L
+    from paper_1010_2107_amd.autograd import vegas_integral
+    _, ng = L.integrand_info(w.integrand, w.dim)
+    grid.reset()
+    grid.stratify(w.ng)
+    theta = torch.tensor(w.theta[:ng], dtype=torch.float64, device="cuda", requires_grad=True)
+    fixed = tuple(w.theta[ng:])
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for it in range(steps):
+        theta.grad = None
+        vegas_integral(theta, grid, w.integrand, w.ncall, w.seed, it, fixed=fixed).backward()
+        if it < w.itmx:
+            grid.refine(w.alpha)
+        if w.itmx2 and it + 1 == w.itmx:
+            grid.combine_reset()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1)
+
+
 def median_loop(grid, w, steps, repeats, **kw):
     """The run_loop of median wall time among `repeats` identical loops
     (same seeds, so the same samples and results), with every wall time."""
@@ -253,6 +282,9 @@ def measure_workload(grid, w, steps, warmup, repeats=5):
         out["fused_evals_per_s"] = n / (ms_f / 1e3)
         out["eager_fwd_adj_evals_per_s"] = n / (ems_a / 1e3)
         out["eager_fused_evals_per_s"] = n / (ems_f / 1e3)
+        autograd_loop(grid, w, steps)  # warm-up
+        ag = sorted(autograd_loop(grid, w, steps) for _ in range(repeats))
+        out["autograd_fwd_adj_evals_per_s"] = n / (ag[len(ag) // 2] / 1e3)
     return out
 
 
@@ -678,7 +710,8 @@ def main(argv=None):
                    "within_3_sigma": None if z is None else bool(z < 3)},
         "roofline": roof,
     }
-    for key in ("fwd_adj_evals_per_s", "fused_evals_per_s", "eager_fwd_adj_evals_per_s", "eager_fused_evals_per_s"):
+    for key in ("fwd_adj_evals_per_s", "fused_evals_per_s", "eager_fwd_adj_evals_per_s", "eager_fused_evals_per_s",
+                "autograd_fwd_adj_evals_per_s"):
         if key in m:
             line[key] = m[key]
     if not args.no_secondary:
@@ -697,7 +730,7 @@ def main(argv=None):
                 if ref:
                     z2 = abs(r2["Ibar"] - ref["Ibar"]) / math.hypot(r2["sigbar"], ref["sigbar"])
             sec[w2.name] = {k: m2[k] for k in ("value", "eager_value", "fwd_adj_evals_per_s", "fused_evals_per_s",
-                                               "graph_matches_eager") if k in m2}
+                                               "autograd_fwd_adj_evals_per_s", "graph_matches_eager") if k in m2}
             sec[w2.name].update({"Ibar": r2["Ibar"], "sigbar": r2["sigbar"], "z": z2,
                                  "kernel_ms_per_launch": m2["kms"] / max(m2["nl"], 1)})
             print(f"[bench] {w2.name}: {m2['value']:.4g} evals/s", file=sys.stderr, flush=True)
