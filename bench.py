@@ -221,10 +221,12 @@ def cpu_baseline_all_cores(w, edges, ncall):
                        f"processes ({res['seconds']:.1f} s)")
 
 
-def autograd_loop(grid, w, steps):
+def autograd_loop(grid, w, steps, fused=True):
     """`steps` iterations through torch.autograd: the forward pass
-    (vegas_integral) and backward() on the differentiable parameters, then
-    the refinement; returns the wall time in ms (HIP events)."""
+    (vegas_integral; fused: the gradient in the forward pass's kernel, else
+    an adjoint pass at backward) and backward() on the differentiable
+    parameters, then the refinement; returns the wall time in ms (HIP
+    events)."""
     import torch
 
     from paper_1010_2107_amd import _lib as L
@@ -240,7 +242,7 @@ def autograd_loop(grid, w, steps):
     t0.record()
     for it in range(steps):
         theta.grad = None
-        vegas_integral(theta, grid, w.integrand, w.ncall, w.seed, it, fixed=fixed).backward()
+        vegas_integral(theta, grid, w.integrand, w.ncall, w.seed, it, fused=fused, fixed=fixed).backward()
         if it < w.itmx:
             grid.refine(w.alpha)
         if w.itmx2 and it + 1 == w.itmx:
@@ -285,6 +287,8 @@ def measure_workload(grid, w, steps, warmup, repeats=5):
         autograd_loop(grid, w, steps)  # warm-up
         ag = sorted(autograd_loop(grid, w, steps) for _ in range(repeats))
         out["autograd_fwd_adj_evals_per_s"] = n / (ag[len(ag) // 2] / 1e3)
+        ag2 = sorted(autograd_loop(grid, w, steps, fused=False) for _ in range(repeats))
+        out["autograd_two_pass_fwd_adj_evals_per_s"] = n / (ag2[len(ag2) // 2] / 1e3)
     return out
 
 
@@ -711,7 +715,7 @@ def main(argv=None):
         "roofline": roof,
     }
     for key in ("fwd_adj_evals_per_s", "fused_evals_per_s", "eager_fwd_adj_evals_per_s", "eager_fused_evals_per_s",
-                "autograd_fwd_adj_evals_per_s"):
+                "autograd_fwd_adj_evals_per_s", "autograd_two_pass_fwd_adj_evals_per_s"):
         if key in m:
             line[key] = m[key]
     if not args.no_secondary:
@@ -730,7 +734,9 @@ def main(argv=None):
                 if ref:
                     z2 = abs(r2["Ibar"] - ref["Ibar"]) / math.hypot(r2["sigbar"], ref["sigbar"])
             sec[w2.name] = {k: m2[k] for k in ("value", "eager_value", "fwd_adj_evals_per_s", "fused_evals_per_s",
-                                               "autograd_fwd_adj_evals_per_s", "graph_matches_eager") if k in m2}
+                                               "autograd_fwd_adj_evals_per_s",
+                                               "autograd_two_pass_fwd_adj_evals_per_s", "graph_matches_eager")
+                            if k in m2}
             sec[w2.name].update({"Ibar": r2["Ibar"], "sigbar": r2["sigbar"], "z": z2,
                                  "kernel_ms_per_launch": m2["kms"] / max(m2["nl"], 1)})
             print(f"[bench] {w2.name}: {m2['value']:.4g} evals/s", file=sys.stderr, flush=True)

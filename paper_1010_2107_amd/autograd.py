@@ -10,13 +10,15 @@ energy, cut values) is passed as `fixed` and is not part of the graph, so
 no gradient is ever reported for a parameter the adjoint does not
 differentiate.
 
-Nothing is stored between the passes except (grid, seed, iteration) and the
-grid-state version of the forward pass: the Philox counters make every
-sample recomputable, and a backward pass after the grid has moved (refine,
-set_edges, reset, stratify) raises VmcError VMC_E_GRID instead of
-differentiating a different estimator.  With `fused=True` the forward pass
-runs the combined forward+adjoint kernel once and the backward pass only
-scales the stored gradient.
+By default (`fused=True`) a forward pass whose input requires a gradient
+runs the combined forward+adjoint kernel once (a few per cent more than the
+forward kernel alone) and the backward pass only scales the stored
+gradient.  With `fused=False` the forward pass runs alone and the backward
+pass runs the adjoint kernel; nothing is stored between the passes except
+(grid, seed, iteration) and the grid-state version of the forward pass: the
+Philox counters make every sample recomputable, and a backward pass after
+the grid has moved (refine, set_edges, reset, stratify) raises VmcError
+VMC_E_GRID instead of differentiating a different estimator.
 """
 from __future__ import annotations
 
@@ -29,7 +31,7 @@ from .grid import Grid
 class VegasIntegral(torch.autograd.Function):
     @staticmethod
     def forward(ctx, theta: torch.Tensor, grid: Grid, integrand: int, ncall: int, seed: int, it: int,
-                fused: bool = False, fixed: tuple = (), fp64: bool = False):
+                fused: bool = True, fixed: tuple = (), fp64: bool = False):
         ntheta, ngrad = L.integrand_info(integrand, grid.dim, fp64)
         if ngrad == 0:
             raise ValueError(f"integrand {integrand} has no differentiable parameters")
@@ -70,10 +72,11 @@ class VegasIntegral(torch.autograd.Function):
         return grad_theta, None, None, None, None, None, None, None, None
 
 
-def vegas_integral(theta, grid, integrand, ncall, seed, it, fused=False, fixed=(), fp64=False):
+def vegas_integral(theta, grid, integrand, ncall, seed, it, fused=True, fixed=(), fp64=False):
     """Differentiable single-iteration estimate I(theta, fixed) on the grid's
     current (frozen) bins.  theta: the ngrad differentiable parameters;
-    fixed: the remaining ones (a tuple of floats); fp64: the double-precision
-    instantiation of the integrand.  Call grid.refine() yourself between
-    iterations, after backward()."""
+    fixed: the remaining ones (a tuple of floats); fused: the gradient in the
+    forward pass's kernel (default) or in a separate adjoint pass at
+    backward(); fp64: the double-precision instantiation of the integrand.
+    Call grid.refine() yourself between iterations, after backward()."""
     return VegasIntegral.apply(theta, grid, integrand, ncall, seed, it, fused, tuple(fixed), fp64)

@@ -132,7 +132,7 @@ def test_backward_after_grid_change_is_refused():
     w = W.C1
     g = Grid(w.dim, w.nbins)
     theta = torch.tensor(w.theta, dtype=torch.float64, device="cuda", requires_grad=True)
-    I = vegas_integral(theta, g, w.integrand, 50_000, 3, 0)
+    I = vegas_integral(theta, g, w.integrand, 50_000, 3, 0, fused=False)
     g.refine(1.5)
     with pytest.raises(VmcError) as e:
         I.backward()
