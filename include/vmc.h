@@ -109,7 +109,7 @@ int vmc_version(void);
 
 /* Bytes of the four device buffers a (dim, nbins) grid needs:
  *   out[0] edges  double[dim][nbins+1]   FP64 bin edges, row per axis
- *   out[1] table  float [dim][nbins][2]  FP32 (lower edge, width x 2^-24) per bin
+ *   out[1] table  float [dim][nbins][2]  FP32 (lower edge, width x 2^-32) per bin
  *   out[2] bins   double[2][dim][nbins]  plane 0: sum w per bin,
  *                                        plane 1: sum w^2 per bin,
  *                 followed by a library-private tail (the blocks' partial

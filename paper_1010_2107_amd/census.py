@@ -51,7 +51,7 @@ def cycle_sum_flops(m):
     return f + 1 + 2 * (K - 1) + 1
 
 
-MAP_PER_AXIS = 5  # delta scale, fma(delta, width, lo), width*N, Jacobian product
+MAP_PER_AXIS = 4  # fma(delta, width, lo), N width, Jacobian product
 
 
 # The flux factor ((1-xa)(1-xb))^3 of an accepted sample: each e^x - 1
@@ -86,11 +86,11 @@ def wjets(n_p: int) -> Census:
     nv = n_p + 1
     f = t = 0
     f += MAP_PER_AXIS * D
-    # parton fractions, sqrt(tau), s, s^(n-3), boost rapidity and the
-    # Jacobian factor L^2 x0 / sqrt(tau); the flux factor ((1-xa)(1-xb))^3 is
-    # formed only for accepted samples (FLUX below)
-    f += 21 - FLUX + (n - 3)
-    t += 4 - FLUX_TRANS
+    # parton fractions ln xa, ln xb, sqrt(tau) (one exp2), sqrt(s) and the
+    # boost rapidity; the rest of the prefactor and the flux factor
+    # ((1-xa)(1-xb))^3 are formed only for accepted samples
+    f += 10
+    t += 1
     # mass chain: one inverse-CDF solve per mass, then M_i = M_{i-1} sqrt(t)
     for K in range(n - 2, 0, -1):
         ff, tt = _mass_step(K)
@@ -101,18 +101,25 @@ def wjets(n_p: int) -> Census:
     # direction, energy and boost factors (13)
     f += 13 + (n - 2) * 34
     t += 3 + (n - 2) * 5
-    # visible particles: pT^2, light-cone components, rapidity, pT (9), the
-    # unit transverse direction (2) and |eta + y_boost| (1)
-    f += 12 * nv
-    t += 3 * nv
+    # visible particles: pT^2, E + |pz|, rapidity (6, one rsqrt and one
+    # log2), the unit transverse direction (2), |eta + y_boost| (1), and for
+    # the partons 1 / pT^2 (1)
+    f += 9 * nv + n_p
+    t += 2 * nv
     # Delta R pairs: Delta eta, z, cos of the threshold angle by its series,
     # cos(Delta phi) from the unit directions
     f += 12 * nv * (nv - 1) // 2
     f_fail, t_fail = f + 1, t
-    # accepted samples: scaled invariants, cyclic sum, Breit-Wigner, product
+    # accepted samples: the smaller light-cone component of each parton (1
+    # and a reciprocal) and its two scaled invariants with a and b (4);
+    # sqrt(s) again from ln xa + ln xb (3 and an exp2); s, c / sqrt(s) and
+    # y_ab (3, one reciprocal); per parton pair the
+    # invariant (8) and its scaled reciprocal (1); the cyclic sum; the
+    # prefactor s^(n-3) s^4 pre L^2 x0 sqrt(S) / sqrt(s) (n - 3 + 8); the
+    # Breit-Wigner factor (2 and a reciprocal) and the product f (6)
     m = n_p + 2
-    f += 3 + 4 * n_p + 9 * (n_p * (n_p - 1) // 2) + cycle_sum_flops(m) + 5 + 4 + 1 + FLUX
-    t += 2 + 2 * n_p + n_p * (n_p - 1) // 2 + 1 + FLUX_TRANS
+    f += 5 * n_p + 3 + 3 + 9 * (n_p * (n_p - 1) // 2) + cycle_sum_flops(m) + (n - 3 + 8) + 8 + FLUX
+    t += n_p + 1 + 1 + n_p * (n_p - 1) // 2 + 1 + FLUX_TRANS
     return Census(int(round(f)), int(round(f_fail)), int(t), int(t_fail))
 
 

@@ -108,26 +108,20 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& B, const BatchDesc& 
   constexpr bool FWD = KIND & KIND_FWD, GRAD = KIND & KIND_ADJ;
   const int N = static_cast<int>(B.nbins);
   const T Nk = static_cast<T>(N) * static_cast<T>(1.0 / kWidthScale);
-  const T Nk2 = Nk * Nk;
   const GaussAxesF<T, D> fn = block_setup<GaussAxesF<T, D>>(B.theta + ds.off_theta);
   for (uint32_t s = tl.s0 + threadIdx.x; s < tl.s1; s += kBlock) {
     uint32_t w[D];
     sample_words<D>(s, B.it, ds.kid, B.key, w);
     int j[D];
     T x[D];
-    T jac = T(1), wprev = T(0);
+    T jac = T(1);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
       T off;
       bin_plain<T>(w[a], B.nbins, j[a], off);
       const auto e = tab[a * N + j[a]];
       x[a] = fma(off, e.y, e.x);
-      if (a & 1) {
-        jac *= (wprev * e.y) * Nk2;
-      } else if (a == D - 1) {
-        jac *= e.y * Nk;
-      }
-      wprev = e.y;
+      jac *= e.y * Nk;
     }
     T g[D + 2];
     const T fv = fn.template eval<GRAD>(x, g);

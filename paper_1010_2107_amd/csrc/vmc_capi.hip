@@ -104,7 +104,7 @@ extern "C" {
 
 const char* vmc_last_error(void) { return g_last_error.c_str(); }
 
-int vmc_version(void) { return 200; }
+int vmc_version(void) { return 300; }
 
 int vmc_workspace_sizes(int dim, int nbins, size_t out[4]) {
   if (!out) return fail(VMC_E_INVALID, "out is NULL");

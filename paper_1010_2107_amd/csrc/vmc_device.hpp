@@ -89,8 +89,8 @@ __device__ __forceinline__ void sample_words(uint32_t s, uint32_t it, uint32_t k
 // in-bin offset its fraction, both exact in 32-bit integer arithmetic for
 // N <= 256.  Stratified: y = (c + u)/ng, so y N = (c 2^24 + 2m+1) N /
 // (ng 2^24); when ng divides N this is c (N/ng) + (2m+1)(N/ng) 2^-24.
-// The helpers return the offset scaled by 2^24 (an integer below 2^24, exact
-// in FP32), to be multiplied by a width stored times kWidthScale.
+// The helpers return the offset scaled by 2^32 (a 24-bit integer times 2^8,
+// exact in FP32), to be multiplied by a width stored times kWidthScale.
 // ---------------------------------------------------------------------------
 // Division of 32-bit words by a launch-constant divisor d >= 2 through a
 // precomputed multiplier (Granlund and Montgomery, "Division by invariant
@@ -131,33 +131,35 @@ __device__ __forceinline__ void digits(uint32_t c, const DivU32& v, uint32_t (&c
   }
 }
 
-// (2m+1) N as m (2N) + N: one 24-bit multiply-add (m < 2^23, 2N <= 512, and
-// the result stays below 2^32).
-__device__ __forceinline__ uint32_t odd_times(uint32_t word, uint32_t n) {
-  return __umul24(word >> 9, 2u * n) + n;
+// (2m+1) N 2^8 as m (N 2^9) + N 2^8, one 32 x 32 + 64-bit multiply-add
+// (m < 2^23, N <= 256, the result below 2^40): its high word is the integer
+// part of (2m+1) N 2^-24, its low word the 24-bit fraction shifted up by 8.
+__device__ __forceinline__ uint64_t odd_times(uint32_t word, uint32_t n) {
+  return static_cast<uint64_t>(word >> 9) * (n << 9) + (n << 8);
 }
 
 template <typename T>
 __device__ __forceinline__ void bin_plain(uint32_t word, uint32_t nbins, int& j, T& off) {
-  const uint32_t P = odd_times(word, nbins);
-  j = static_cast<int>(P >> 24);
-  off = static_cast<T>(static_cast<int>(P & 0xFFFFFFu));
+  const uint64_t P = odd_times(word, nbins);
+  j = static_cast<int>(P >> 32);
+  off = static_cast<T>(static_cast<uint32_t>(P));
 }
 
 template <typename T>
 __device__ __forceinline__ void bin_strat_div(uint32_t word, uint32_t ca, uint32_t per_cube, int& j, T& off) {
   // ng divides nbins; per_cube = nbins / ng
-  const uint32_t P = odd_times(word, per_cube);
-  j = static_cast<int>(__umul24(ca, per_cube) + (P >> 24));
-  off = static_cast<T>(static_cast<int>(P & 0xFFFFFFu));
+  const uint64_t P = odd_times(word, per_cube);
+  j = static_cast<int>(__umul24(ca, per_cube) + static_cast<uint32_t>(P >> 32));
+  off = static_cast<T>(static_cast<uint32_t>(P));
 }
 
 // ng does not divide nbins: the point lies at (ca + (2m+1) 2^-24) / ng on
 // the axis, and Q = (ca 2^24 + 2m + 1) N is that position times N ng 2^24.
 // The bin is floor(Q / (ng 2^24)) = floor(floor(Q / 2^24) / ng), where
 // floor(Q / 2^24) < ng N fits 32 bits when ng N < 2^32, and the offset, in
-// units of 2^-24 of the bin, is (Q mod ng 2^24) / ng, formed from its two
-// parts with the reciprocal of ng.
+// units of 2^-32 of the bin, is 2^8 (Q mod ng 2^24) / ng, formed from its
+// two parts with the reciprocal of ng (the factors 2^8 and 2^32 are exact,
+// so the result is 2^8 times the offset in units of 2^-24, bit for bit).
 template <typename T>
 __device__ __forceinline__ void bin_strat_gen(uint32_t word, uint32_t ca, const DivU32& ng, uint32_t nbins,
                                               T inv_ng, int& j, T& off) {
@@ -165,9 +167,9 @@ __device__ __forceinline__ void bin_strat_gen(uint32_t word, uint32_t ca, const 
   const uint32_t hi = static_cast<uint32_t>(Q >> 24);
   const uint32_t q = divu32(hi, ng);
   j = static_cast<int>(q);
-  const T rhi = static_cast<T>(hi - q * ng.d);                             // < ng
-  const T rlo = static_cast<T>(static_cast<int>(static_cast<uint32_t>(Q) & 0xFFFFFFu));  // < 2^24
-  off = fma(rhi, inv_ng * static_cast<T>(16777216.0), rlo * inv_ng);
+  const T rhi = static_cast<T>(hi - q * ng.d);                     // < ng
+  const T rlo = static_cast<T>(static_cast<uint32_t>(Q) << 8);  // (Q mod 2^24) 2^8
+  off = fma(rhi, inv_ng * static_cast<T>(4294967296.0), rlo * inv_ng);
 }
 
 // The same map when ng N >= 2^32 (one axis cut into more than 2^32 / N
@@ -179,14 +181,14 @@ __device__ __forceinline__ void bin_strat_wide(uint32_t word, uint32_t ca, uint3
   const uint64_t Dn = static_cast<uint64_t>(ng) << 24;
   const uint64_t q = Q / Dn;
   j = static_cast<int>(q);
-  off = static_cast<T>(static_cast<double>(Q - q * Dn) / static_cast<double>(ng));
+  off = static_cast<T>(static_cast<double>(Q - q * Dn) * 256.0 / static_cast<double>(ng));
 }
 
 // A grid's table holds per bin the lower edge and the width times
-// kWidthScale = 2^-24, so that a sample's point is fma(off, width', edge) with
-// the offset `off` of the bin helpers: the same value as edge + (off 2^-24)
+// kWidthScale = 2^-32, so that a sample's point is fma(off, width', edge) with
+// the offset `off` of the bin helpers: the same value as edge + (off 2^-32)
 // width, since both scalings are exact, one multiply fewer per axis.
-constexpr double kWidthScale = 0x1p-24;
+constexpr double kWidthScale = 0x1p-32;
 
 // Grid table entry: lower edge and scaled width of a bin.
 template <typename T>

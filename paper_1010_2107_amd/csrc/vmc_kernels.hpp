@@ -190,10 +190,8 @@ __device__ __forceinline__ void make_point(const SampleArgs& A, const typename T
                                            const uint32_t (&w)[D], const uint32_t (&cc)[D], int (&j)[D],
                                            T (&x)[D], T& jac) {
   const int N = static_cast<int>(A.nbins);
-  const T Nk = static_cast<T>(N) * static_cast<T>(1.0 / kWidthScale);  // per-axis Jacobian factor
-  const T Nk2 = Nk * Nk;  // <= 2^64 for N <= 256: exact
+  const T Nk = static_cast<T>(N) * static_cast<T>(1.0 / kWidthScale);  // per-axis Jacobian factor, exact
   jac = T(1);
-  T wprev = T(0);
   // stratified: the bins of all axes first, with the (launch-uniform) choice
   // of bin map taken once, so that the table reads below form one
   // straight-line run
@@ -221,14 +219,7 @@ __device__ __forceinline__ void make_point(const SampleArgs& A, const typename T
     }
     const auto e = tab[a * N + j[a]];
     x[a] = fma(off, e.y, e.x);
-    // J = prod N width, two axes per multiply: a product of two scaled
-    // widths is w_a w_b 2^-48, a normal FP32 number for widths above 2^-39
-    if (a & 1) {
-      jac *= (wprev * e.y) * Nk2;
-    } else if (a == D - 1) {
-      jac *= e.y * Nk;
-    }
-    wprev = e.y;
+    jac *= e.y * Nk;  // J = prod N width; N width is exact from the scaled width
   }
 }
 

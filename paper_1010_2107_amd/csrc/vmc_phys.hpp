@@ -103,7 +103,9 @@ __device__ __forceinline__ T cycle_sum6(const T (&y)[6][6]) {
 // residual is (1 - F(1-u)) - (1 - r), with 1 - F(1-u) written as a
 // polynomial in u that starts at u^2, so that no low-order terms cancel.
 // On both sides the residual is v^2 H(v) - target, H of degree k-1, and each
-// lane picks its coefficients once.  The start inverts the leading term and
+// lane picks its coefficients once (the FP64 build's steps; the FP32 build's
+// one step has an FP64 residual, which needs no such care, and takes it in
+// t on both sides).  The start inverts the leading term and
 // corrects it with a fitted polynomial (vmc_mass_start.hpp); its relative
 // error is below 1.5e-4, so one Newton step reaches FP32 round-off and
 // three reach FP64 round-off.  Returns t and u = 1 - t.
@@ -193,25 +195,26 @@ __device__ __forceinline__ TU<T> mass_fraction(T r) {
     T v = fmin(s * (lo ? rl : rh), T(1));
     const T target = lo ? r : q;
     if constexpr (F32) {
-      // residual in FP64; its derivative in FP32 from the closed form: on
-      // both sides dR/dv = F'(t) = K (K+1) t^(K-1) (1 - t) with t = v (low)
-      // or 1 - v (high)
+      // The step in t on both sides: t = v or 1 - v (exact in FP64), the
+      // residual F(t) - r = t^K ((K+1) - K t) - r in FP64, the derivative
+      // F'(t) = K (K+1) t^(K-1) (1 - t) in FP32.  Near t = 1, F(t) rounds to
+      // an absolute 6e-16, which is 5e-9 of the smallest 1 - r of an FP32 r
+      // (2^-24); the step's own error dominates.
       const double vd = static_cast<double>(v);
-      double H = lo ? low_coef<K>(K - 1) : comp_coef<K>(K + 1);
+      const double td = lo ? vd : 1.0 - vd;
+      double tk = td;
 #pragma unroll
-      for (int j = K - 2; j >= 0; --j) H = fma(H, vd, lo ? low_coef<K>(j) : comp_coef<K>(j + 2));
-      const double res = fma(vd * vd, H, -static_cast<double>(target));
+      for (int j = 1; j < K; ++j) tk *= td;
+      const double res = fma(tk, fma(-static_cast<double>(K), td, K + 1.0), -static_cast<double>(r));
       const T om = T(1) - v;
       const T tt = lo ? v : om, uu = lo ? om : v;
       T tp = T(K * (K + 1));
 #pragma unroll
       for (int j = 0; j < K - 1; ++j) tp *= tt;
-      const T dP = tp * uu;  // > 0 inside (0, 1); 0 at v = 0 where res = 0
-      double v64 = vd - res * static_cast<double>(vrcp(fmax(dP, T(1e-30))));
-      v64 = fmin(fmax(v64, 0.0), 1.0);
-      const double t64 = lo ? v64 : 1.0 - v64;
-      return lo ? TU<T>{static_cast<T>(v64), static_cast<T>(1.0 - v64), t64}
-                : TU<T>{static_cast<T>(t64), static_cast<T>(v64), t64};
+      const T dP = tp * uu;  // > 0 inside (0, 1); 0 at t = 0 or 1, where res = 0
+      double t64 = td - res * static_cast<double>(vrcp(fmax(dP, T(1e-30))));
+      t64 = fmin(fmax(t64, 0.0), 1.0);
+      return TU<T>{static_cast<T>(t64), static_cast<T>(1.0 - t64), t64};
     } else {
       T h[K];
 #pragma unroll
@@ -363,7 +366,7 @@ __device__ __forceinline__ double shat_fp64(float x0, float x1, float Lh, float 
 // +-ln(larger / pT).
 template <typename T>
 struct LightCone {
-  T pt2, pt, rpt, rpt2, lp, lm, eta;
+  T pt2, pt, rpt, rpt2, big, lp, lm, eta;
 };
 template <typename T>
 __device__ __forceinline__ LightCone<T> light_cone(const T (&v)[4]) {
@@ -374,6 +377,7 @@ __device__ __forceinline__ LightCone<T> light_cone(const T (&v)[4]) {
   const T small = r.pt2 * vrcp(big);
   const T rpt = vrsqrt(r.pt2);
   const T ya = vlog_fast(big * rpt);
+  r.big = big;
   r.lp = z > T(0) ? big : small;
   r.lm = z > T(0) ? small : big;
   r.eta = copysign(ya, z);
@@ -438,36 +442,55 @@ struct WJetsF {
   }
 
   // The evaluation in two stages so that a kernel can queue the samples
-  // that pass the cuts and run the colour sum on full waves: stage 1 maps
-  // x to momenta, applies the cuts and keeps the scaled invariants y_kl of
-  // the coloured set (upper triangle), m_enu^2 - M^2, the prefactor without
-  // the flux and the two logarithms the flux needs; stage 2 forms the flux,
-  // |M|^2 and f from them (the two e^x - 1 run on full waves there).
-  static constexpr int NY = MC * (MC - 1) / 2;
+  // that pass the cuts and run everything else on full waves: stage 1 maps
+  // x to momenta and applies the cuts, keeping what the rest needs (per
+  // parton E + |pz| signed as pz, 1 / pT^2 and the transverse momentum;
+  // x0, m_enu^2 - M^2 and ln xa, ln xb, from which stage 2 forms sqrt(s)
+  // again, bit for bit, as well as the flux factor);
+  // stage 2 forms the invariants of the coloured set, the prefactor, the
+  // flux, |M|^2 and f.  Most samples fail the cuts (about 60 % for four
+  // partons), so work moved from stage 1 to stage 2 is done on fewer lanes.
   struct State {
-    T y[NY];
-    T dm, pref;  // dm = m_enu^2 - M^2; pref = pre s^(n-3) L^2 x0 / sqrt(tau) s^4 / c^m
+    T bp[NP];    // E + |pz|, with the sign of pz (the larger light-cone component)
+    T rpt2[NP];  // 1 / pT^2
+    T px[NP], py[NP];
+    T x0;
+    T dm;        // m_enu^2 - M^2
     T la, lb;    // ln xa, ln xb: the flux factor is ((1 - xa)(1 - xb))^3
   };
-  static constexpr int kStateWords = NY + 4;
+  static constexpr int kStateWords = 4 * NP + 4;
   static constexpr bool kStaged = FULL && sizeof(T) == 4;  // the queue holds FP32
 
   __device__ __forceinline__ static void store_state(const State& st, float* q, int stride, int e) {
+    int k = 0;
+    auto put = [&](T v) { q[(k++) * stride + e] = static_cast<float>(v); };
 #pragma unroll
-    for (int i = 0; i < NY; ++i) q[i * stride + e] = static_cast<float>(st.y[i]);
-    q[NY * stride + e] = static_cast<float>(st.dm);
-    q[(NY + 1) * stride + e] = static_cast<float>(st.pref);
-    q[(NY + 2) * stride + e] = static_cast<float>(st.la);
-    q[(NY + 3) * stride + e] = static_cast<float>(st.lb);
+    for (int j = 0; j < NP; ++j) {
+      put(st.bp[j]);
+      put(st.rpt2[j]);
+      put(st.px[j]);
+      put(st.py[j]);
+    }
+    put(st.x0);
+    put(st.dm);
+    put(st.la);
+    put(st.lb);
   }
   __device__ __forceinline__ static State load_state(const float* q, int stride, int e) {
     State st;
+    int k = 0;
+    auto get = [&]() { return static_cast<T>(q[(k++) * stride + e]); };
 #pragma unroll
-    for (int i = 0; i < NY; ++i) st.y[i] = static_cast<T>(q[i * stride + e]);
-    st.dm = static_cast<T>(q[NY * stride + e]);
-    st.pref = static_cast<T>(q[(NY + 1) * stride + e]);
-    st.la = static_cast<T>(q[(NY + 2) * stride + e]);
-    st.lb = static_cast<T>(q[(NY + 3) * stride + e]);
+    for (int j = 0; j < NP; ++j) {
+      st.bp[j] = get();
+      st.rpt2[j] = get();
+      st.px[j] = get();
+      st.py[j] = get();
+    }
+    st.x0 = get();
+    st.dm = get();
+    st.la = get();
+    st.lb = get();
     return st;
   }
 
@@ -480,10 +503,6 @@ struct WJetsF {
     const T ltau = la + lb;
     const T h = vexp2_fast(ltau * T(0.5 * 1.4426950408889634));  // sqrt(tau)
     const T rs = sqrtS * h;           // sqrt(s)
-    const T shat = rs * rs;
-    T spow = T(1);
-#pragma unroll
-    for (int i = 0; i < NOUT - 3; ++i) spow *= shat;
     const T yb = T(0.5) * (la - lb);
     // ---- RAMBO on diet: masses M_1 = sqrt(s) > M_2 > ... > M_{n-1} > M_n = 0
     T Mi[NOUT + 1], Ui[NOUT + 1];
@@ -499,7 +518,7 @@ struct WJetsF {
 
     // ---- visible particles: partons 0..NP-1 and the electron NP
     constexpr int NV = NP + 1;
-    T pt2[NV], rpt2[NV], lp[NV], lm[NV], eta[NV], ux[NV], uy[NV];
+    T pt2[NV], eta[NV], ux[NV], uy[NV];
     // the pT and rapidity cuts on the smallest pT^2 and the largest |eta|;
     // fmin and fmax skip a NaN (degenerate momenta), which then fails the
     // Delta R test below (every visible particle is in a pair there)
@@ -508,10 +527,13 @@ struct WJetsF {
     for (int j = 0; j < NV; ++j) {
       const LightCone<T> lc = light_cone(p[j]);
       pt2[j] = lc.pt2;
-      rpt2[j] = lc.rpt2;
-      lp[j] = lc.lp;
-      lm[j] = lc.lm;
       eta[j] = lc.eta;
+      if (j < NP) {
+        st.bp[j] = p[j][3] > T(0) ? lc.big : -lc.big;
+        st.rpt2[j] = lc.rpt2;
+        st.px[j] = p[j][1];
+        st.py[j] = p[j][2];
+      }
       ux[j] = p[j][1] * lc.rpt;  // transverse direction
       uy[j] = p[j][2] * lc.rpt;
       const T ya = fabs(eta[j] + yb);
@@ -546,50 +568,57 @@ struct WJetsF {
         c = fma(c, -z, T(1));
         pass = pass & (fma(ux[i], ux[j], uy[i] * uy[j]) < c);
       }
-    if (!pass) return false;
-
-    // ---- invariants of the coloured set, scaled: y = c / s_kl with c a power
-    // of two near s^(4/m), so s^4 / prod s = (s^4 / c^m) prod y exactly
-    const int ce = (4 * ilogb_(shat)) / MC;
-    const T c = ldexp_(T(1), ce);
-    const T crs = c * vrcp(rs);
-    int k = 0;
-    st.y[k++] = crs * vrcp(rs);  // (0,1)
-#pragma unroll
-    for (int j = 0; j < NP; ++j) st.y[k++] = crs * lp[j] * rpt2[j];  // (0, 2+j): c / s_aj, s_aj = sqrt(s)(E - pz)
-#pragma unroll
-    for (int j = 0; j < NP; ++j) st.y[k++] = crs * lm[j] * rpt2[j];  // (1, 2+j): c / s_bj
-#pragma unroll
-    for (int i = 0; i < NP; ++i)
-#pragma unroll
-      for (int j = i + 1; j < NP; ++j) {
-        const T sij = fma(lp[i], lm[j], lm[i] * lp[j]) - T(2) * (p[i][1] * p[j][1] + p[i][2] * p[j][2]);
-        st.y[k++] = c * vrcp(sij);  // (2+i, 2+j)
-      }
     if constexpr (sizeof(T) == 8) st.dm = fma(Mi[NOUT - 1], Mi[NOUT - 1], -Mv2);
-    const T s2 = shat * shat;
-    st.pref = ((pre * spow) * (LL * x[0] * vrcp(h))) * ldexp_(s2 * s2, -ce * MC);
+    st.x0 = x[0];
     st.la = la;
     st.lb = lb;
-    return true;
+    return pass;
   }
 
   // |M|^2 and f of a sample that passed the cuts
   template <bool GRAD>
   __device__ __forceinline__ T stage2(const State& st, T (&g)[NGRAD + 1]) const {
+    // ---- light-cone components E +- pz of the partons: the larger one is
+    // kept, the smaller is pT^2 over it
+    T lp[NP], lm[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const T big = fabs(st.bp[j]);
+      const T small = vrcp(st.rpt2[j] * big);
+      lp[j] = st.bp[j] > T(0) ? big : small;
+      lm[j] = st.bp[j] > T(0) ? small : big;
+    }
+    // ---- invariants of the coloured set, scaled: y = c / s_kl with c a power
+    // of two near s^(4/m), so s^4 / prod s = (s^4 / c^m) prod y exactly
+    // sqrt(s) as stage 1 formed it (the same operations on the same values)
+    const T rs = sqrtS * vexp2_fast((st.la + st.lb) * T(0.5 * 1.4426950408889634));
+    const T shat = rs * rs, rrs = vrcp(rs);
+    const int ce = (4 * ilogb_(shat)) / MC;
+    const T c = ldexp_(T(1), ce);
+    const T crs = c * rrs;
     T y[MC][MC];
-    int k = 0;
-    y[0][1] = y[1][0] = st.y[k++];
+    y[0][1] = y[1][0] = crs * rrs;
 #pragma unroll
-    for (int j = 0; j < NP; ++j, ++k) y[0][2 + j] = y[2 + j][0] = st.y[k];
-#pragma unroll
-    for (int j = 0; j < NP; ++j, ++k) y[1][2 + j] = y[2 + j][1] = st.y[k];
+    for (int j = 0; j < NP; ++j) {
+      y[0][2 + j] = y[2 + j][0] = crs * lp[j] * st.rpt2[j];  // c / s_aj, s_aj = sqrt(s)(E - pz)
+      y[1][2 + j] = y[2 + j][1] = crs * lm[j] * st.rpt2[j];  // c / s_bj
+    }
 #pragma unroll
     for (int i = 0; i < NP; ++i)
 #pragma unroll
-      for (int j = i + 1; j < NP; ++j, ++k) y[2 + i][2 + j] = y[2 + j][2 + i] = st.y[k];
+      for (int j = i + 1; j < NP; ++j) {
+        const T sij = fma(lp[i], lm[j], lm[i] * lp[j]) - T(2) * (st.px[i] * st.px[j] + st.py[i] * st.py[j]);
+        y[2 + i][2 + j] = y[2 + j][2 + i] = c * vrcp(sij);
+      }
 #pragma unroll
     for (int i = 0; i < MC; ++i) y[i][i] = T(0);
+    // prefactor pre s^(n-3) L^2 x0 / sqrt(tau) s^4 / c^m (1 / sqrt(tau) =
+    // sqrt(S) / sqrt(s))
+    T spow = T(1);
+#pragma unroll
+    for (int i = 0; i < NOUT - 3; ++i) spow *= shat;
+    const T s2 = shat * shat;
+    const T pref = ((pre * spow) * (LL * st.x0 * (sqrtS * rrs))) * ldexp_(s2 * s2, -ce * MC);
     T ptsum;
     if constexpr (MC == 6) {
       ptsum = cycle_sum6<T>(y);
@@ -600,7 +629,7 @@ struct WJetsF {
     const T dm = st.dm;
     const T invD = vrcp(fma(dm, dm, M2G2));
     const T om = vexpm1_fast(st.la) * vexpm1_fast(st.lb);  // (1 - xa)(1 - xb) without cancellation
-    const T f = (st.pref * (om * om * om)) * (MGpi * invD) * ptsum;
+    const T f = (pref * (om * om * om)) * (MGpi * invD) * ptsum;
     if (GRAD) {
       g[0] = f * (invM - fma(T(-4) * M, dm, twoMG2) * invD);
       g[1] = f * (invG - T(2) * M * MG * invD);

@@ -201,8 +201,8 @@ def test_refine_matches_oracle_on_given_bins():
         assert np.max(np.abs(got - ref)) <= 1e-12
         tab = g.table.cpu().numpy()
         assert np.array_equal(tab[..., 0], ref[:, :-1].astype(np.float32))
-        # widths are stored times 2^-24 (the bin offset is a 24-bit integer)
-        assert np.array_equal(tab[..., 1], (np.diff(ref, axis=1) * 2.0**-24).astype(np.float32))
+        # widths are stored times 2^-32 (the bin offset is a 24-bit integer times 2^8)
+        assert np.array_equal(tab[..., 1], (np.diff(ref, axis=1) * 2.0**-32).astype(np.float32))
     # the hand-worked cases, each written out step by step from the definition
     from tests.test_oracle_refine_combine import HAND_CASES
     for name, case in sorted(HAND_CASES.items()):
