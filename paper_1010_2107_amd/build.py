@@ -2,7 +2,11 @@
 
 Each ``csrc/*.hip`` unit is compiled to an object in ``_build/`` in parallel,
 then linked into ``libvmc.so`` next to this file.  Packed FP32 instructions
-are disabled for every unit.
+are disabled for every unit.  A multiply and an add fuse only within one
+source expression (``-ffp-contract=on``): the fusion is then fixed before
+code generation, so every kernel that inlines the same integrand code rounds
+it alike (the sample kernels, the per-sample dump that tests replay, and the
+two paths by which a queued sample reaches its matrix element).
 """
 from __future__ import annotations
 
@@ -24,7 +28,7 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-munsafe-fp-atomics", "-Wall", "-Wno-unused-result",
+    "-munsafe-fp-atomics", "-ffp-contract=on", "-Wall", "-Wno-unused-result",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
 ]
 

@@ -124,14 +124,16 @@ def wjets(n_p: int) -> Census:
 
 
 def whel(n: int) -> Census:
-    """u dbar -> W + n gluons (helicity amplitudes), per the HIP source:
-    complex multiply = 6 flops (4 mul, 2 add), complex add = 2."""
+    """u dbar -> W + n gluons (helicity amplitudes), per the HIP source.
+    Complex arithmetic: a product 6 flops (two multiplies, two fmas), a
+    fused a b + c 8 (four fmas), s a + c 4; every product feeding a sum is
+    fused into it in the source."""
     nf = n + 2
     D = 3 * n + 5
     f = t = 0
     f += MAP_PER_AXIS * D
-    f += 21 - FLUX  # parton fractions and the Jacobian factor, as for wjets
-    t += 4 - FLUX_TRANS
+    f += 9  # parton fractions, sqrt(tau) (one exp2), sqrt(s), boost rapidity
+    t += 1
     for K in range(nf - 2, 0, -1):  # mass chain
         ff, tt = _mass_step(K)
         f += ff + 1
@@ -144,24 +146,29 @@ def whel(n: int) -> Census:
         f += 12  # Durham pT_ij between the two gluons
         t += 3
     f_fail, t_fail = f + 1, t
-    SBAR, TOP, PROP, SBAR_U = 36, 18, 35, 4
+    # (V.sigmabar) x: 28; plus a spinor: 32; its first component: 14, plus a
+    # complex number: 16; a propagator (P^2, its reciprocal, P.sigma x): 29
+    SBAR, SBAR_ADD, TOP, TOP_ADD, PROP = 28, 32, 14, 16, 29
     f += 2 * 12 + 40  # lepton spinors and current
     t += 2
     if n == 0:
         f += TOP + 3
     elif n == 1:
-        f += 15 + (SBAR_U + PROP + TOP) + (SBAR_U + PROP + TOP) + 4
+        f += 15 + 2 * PROP + TOP + TOP_ADD + 4  # polarisation, two chains, |A|^2
         t += 3 + 2
     else:
-        f += 2 * 15 + 60  # polarisations, three-gluon current
-        f += 3 * (SBAR_U + PROP)  # shared prefixes
-        # the two colour orders: four chains each ending in its own vertex
-        # and propagator, the chains sharing both summed before them (four
-        # spinor additions), the three-gluon terms (one sbar_u, one top),
-        # the complex sums and the colour matrix
-        f += 6 * SBAR + 4 * (PROP + TOP) + (SBAR_U + TOP) + 4 * 4 + 8 + 10
+        # polarisations (2 x 15); the three-gluon current: the dot products
+        # (3 x 16), its scalars (8), K^2 (12) and its four components (4 x 18)
+        f += 2 * 15 + 48 + 8 + 12 + 72
+        f += 3 * PROP  # the chains' shared first propagators
+        # each colour order: two vertex-propagator chains and a vertex, the
+        # sums fused into the vertices (2 x SBAR_ADD + SBAR + 2 x PROP +
+        # 2 x TOP_ADD); the three-gluon term TOP; the colour matrix (10)
+        f += 2 * (2 * SBAR_ADD + SBAR + 2 * PROP + 2 * TOP_ADD) + TOP + 10
         t += 2 * 3 + 1 + 9
-    f += 8 + FLUX  # W propagator, prefactor, flux factor
+    f += 9 + n + 2  # sqrt(s) again (an exp2), s^n and the prefactor (a reciprocal)
+    t += 2
+    f += 8 + FLUX  # W propagator, product, flux factor
     t += 1 + FLUX_TRANS
     return Census(int(round(f)), int(round(f_fail)), int(t), int(t_fail))
 

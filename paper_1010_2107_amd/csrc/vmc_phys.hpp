@@ -279,11 +279,16 @@ __device__ __forceinline__ void mass_chain(const T (&x)[D], T (&Mi)[NOUT + 1], T
     const TU<T> tu = mass_fraction<NOUT - I, T>(x[X0 + I - 2]);
     Mi[I] = Mi[I - 1] * vsqrt(tu.t);
     Ui[I] = tu.u;
-    if constexpr (RES64) res.m2 *= tu.t64;
+    if constexpr (RES64 && I < NOUT - 1) res.m2 *= tu.t64;
+    if constexpr (RES64 && I == NOUT - 1) {  // the last pair: m^2 - M^2, its product fused
+      float dm = static_cast<float>(fma(res.m2, tu.t64, -res.Mv2));
+      asm volatile("" : "+v"(dm));  // formed here, where its inputs are live anyway
+      res.dm = dm;
+    }
     mass_chain<NOUT, X0, I + 1, RES64>(x, Mi, Ui, res);
-  } else if constexpr (RES64) {
+  } else if constexpr (RES64 && NOUT == 2) {  // no mass step: m^2 = s
     float dm = static_cast<float>(res.m2 - res.Mv2);
-    asm volatile("" : "+v"(dm));  // formed here, where its inputs are live anyway
+    asm volatile("" : "+v"(dm));
     res.dm = dm;
   }
 }
@@ -503,7 +508,7 @@ struct WJetsF {
     const T ltau = la + lb;
     const T h = vexp2_fast(ltau * T(0.5 * 1.4426950408889634));  // sqrt(tau)
     const T rs = sqrtS * h;           // sqrt(s)
-    const T yb = T(0.5) * (la - lb);
+    const T dl = la - lb;  // twice the boost rapidity y_b
     // ---- RAMBO on diet: masses M_1 = sqrt(s) > M_2 > ... > M_{n-1} > M_n = 0
     T Mi[NOUT + 1], Ui[NOUT + 1];
     T p[NOUT][4];
@@ -536,7 +541,7 @@ struct WJetsF {
       }
       ux[j] = p[j][1] * lc.rpt;  // transverse direction
       uy[j] = p[j][2] * lc.rpt;
-      const T ya = fabs(eta[j] + yb);
+      const T ya = fabs(fma(T(0.5), dl, eta[j]));  // |eta + y_b|
       pt2_min = j == 0 ? pt2[0] : fmin(pt2_min, pt2[j]);
       yabs_max = j == 0 ? ya : fmax(yabs_max, ya);
     }

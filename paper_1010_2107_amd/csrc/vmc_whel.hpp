@@ -50,6 +50,17 @@ template <typename T>
 __device__ __forceinline__ T norm2(Cx<T> a) {
   return fma(a.r, a.r, a.i * a.i);
 }
+// a b + c and s a + c with every product fused into its sum (the library is
+// built so that only fusions written out like these happen, which keeps
+// every kernel's rounding of this code the same)
+template <typename T>
+__device__ __forceinline__ Cx<T> cfma(Cx<T> a, Cx<T> b, Cx<T> c) {
+  return {fma(a.r, b.r, fma(-a.i, b.i, c.r)), fma(a.r, b.i, fma(a.i, b.r, c.i))};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> cfma(T s, Cx<T> a, Cx<T> c) {
+  return {fma(s, a.r, c.r), fma(s, a.i, c.i)};
+}
 
 template <typename T>
 struct Sp {  // a 2-component spinor
@@ -73,15 +84,24 @@ struct SB {
   Cx<T> p, m, lo, hi;
 };
 
-// (V . sigmabar) x
+// (V . sigmabar) x, and (V . sigmabar) x + y
 template <typename T>
 __device__ __forceinline__ Sp<T> sbar(const SB<T>& V, const Sp<T>& x) {
-  return {V.p * x.a + V.lo * x.b, V.hi * x.a + V.m * x.b};
+  return {cfma(V.lo, x.b, V.p * x.a), cfma(V.m, x.b, V.hi * x.a)};
 }
-// first component only (the last vertex before v_L(p_dbar) = (r, 0))
+template <typename T>
+__device__ __forceinline__ Sp<T> sbar_add(const SB<T>& V, const Sp<T>& x, const Sp<T>& y) {
+  return {cfma(V.lo, x.b, cfma(V.p, x.a, y.a)), cfma(V.m, x.b, cfma(V.hi, x.a, y.b))};
+}
+// first component only (the last vertex before v_L(p_dbar) = (r, 0)), and
+// that plus c
 template <typename T>
 __device__ __forceinline__ Cx<T> sbar_top(const SB<T>& V, const Sp<T>& x) {
-  return V.p * x.a + V.lo * x.b;
+  return cfma(V.lo, x.b, V.p * x.a);
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> sbar_top_add(const SB<T>& V, const Sp<T>& x, Cx<T> c) {
+  return cfma(V.lo, x.b, cfma(V.p, x.a, c));
 }
 // (V . sigmabar) (0, 1): the first vertex on u_L(p_u) = (0, r)
 template <typename T>
@@ -102,7 +122,7 @@ __device__ __forceinline__ Sp<T> prop(const LC<T>& P, const Sp<T>& x) {
   const T m = P.m * inv, p = P.p * inv;
   const Cx<T> lo = {-P.x * inv, P.y * inv};   // -(P1 - i P2) / P^2
   const Cx<T> hi = {-P.x * inv, -P.y * inv};  // -(P1 + i P2) / P^2
-  return {m * x.a + lo * x.b, hi * x.a + p * x.b};
+  return {cfma(lo, x.b, m * x.a), cfma(p, x.b, hi * x.a)};
 }
 // light-cone components of a massless momentum: the larger of E +- pz
 // directly, the smaller as pT^2 over it
@@ -195,13 +215,15 @@ struct WHelF {
 
   // The evaluation in two stages so that a kernel can queue the samples
   // that pass the cuts and evaluate the amplitudes on full waves: stage 1
-  // maps x to momenta and applies the cuts; stage 2 forms |M|^2 and f.
+  // maps x to momenta and applies the cuts; stage 2 forms sqrt(s) again
+  // from ln xa + ln xb (the same operations as stage 1, bit for bit), the
+  // prefactor, |M|^2 and f.
   struct State {
     T p[NOUT][4];  // g_1..g_NG, mu+, nu in the partonic frame
-    T Eh, dm, pref, hel;  // sqrt(s)/2, m_munu^2 - M^2, prefactor without the flux, helicity configuration
-    T la, lb;             // ln xa, ln xb: the flux factor ((1 - xa)(1 - xb))^3 is formed in stage 2
+    T x0, dm, hel;  // x0, m_munu^2 - M^2, helicity configuration
+    T la, lb;       // ln xa, ln xb: sqrt(s) and the flux factor ((1 - xa)(1 - xb))^3 are formed in stage 2
   };
-  static constexpr int kStateWords = 4 * NOUT + 6;
+  static constexpr int kStateWords = 4 * NOUT + 5;
   static constexpr bool kStaged = sizeof(T) == 4;  // the queue holds FP32
 
   __device__ __forceinline__ static void store_state(const State& st, float* q, int stride, int e) {
@@ -209,12 +231,11 @@ struct WHelF {
     for (int i = 0; i < NOUT; ++i)
 #pragma unroll
       for (int c = 0; c < 4; ++c) q[(4 * i + c) * stride + e] = static_cast<float>(st.p[i][c]);
-    q[(4 * NOUT + 0) * stride + e] = static_cast<float>(st.Eh);
+    q[(4 * NOUT + 0) * stride + e] = static_cast<float>(st.x0);
     q[(4 * NOUT + 1) * stride + e] = static_cast<float>(st.dm);
-    q[(4 * NOUT + 2) * stride + e] = static_cast<float>(st.pref);
-    q[(4 * NOUT + 3) * stride + e] = static_cast<float>(st.hel);
-    q[(4 * NOUT + 4) * stride + e] = static_cast<float>(st.la);
-    q[(4 * NOUT + 5) * stride + e] = static_cast<float>(st.lb);
+    q[(4 * NOUT + 2) * stride + e] = static_cast<float>(st.hel);
+    q[(4 * NOUT + 3) * stride + e] = static_cast<float>(st.la);
+    q[(4 * NOUT + 4) * stride + e] = static_cast<float>(st.lb);
   }
   __device__ __forceinline__ static State load_state(const float* q, int stride, int e) {
     State st;
@@ -222,12 +243,11 @@ struct WHelF {
     for (int i = 0; i < NOUT; ++i)
 #pragma unroll
       for (int c = 0; c < 4; ++c) st.p[i][c] = static_cast<T>(q[(4 * i + c) * stride + e]);
-    st.Eh = static_cast<T>(q[(4 * NOUT + 0) * stride + e]);
+    st.x0 = static_cast<T>(q[(4 * NOUT + 0) * stride + e]);
     st.dm = static_cast<T>(q[(4 * NOUT + 1) * stride + e]);
-    st.pref = static_cast<T>(q[(4 * NOUT + 2) * stride + e]);
-    st.hel = static_cast<T>(q[(4 * NOUT + 3) * stride + e]);
-    st.la = static_cast<T>(q[(4 * NOUT + 4) * stride + e]);
-    st.lb = static_cast<T>(q[(4 * NOUT + 5) * stride + e]);
+    st.hel = static_cast<T>(q[(4 * NOUT + 2) * stride + e]);
+    st.la = static_cast<T>(q[(4 * NOUT + 3) * stride + e]);
+    st.lb = static_cast<T>(q[(4 * NOUT + 4) * stride + e]);
     return st;
   }
 
@@ -236,8 +256,7 @@ struct WHelF {
     const T lb = L * x[0] * (T(1) - x[1]);
     const T h = vexp2_fast((la + lb) * T(0.5 * 1.4426950408889634));  // sqrt(tau)
     const T rs = sqrtS * h;
-    const T shat = rs * rs;
-    const T yb = T(0.5) * (la - lb);
+    const T dl = la - lb;  // twice the boost rapidity y_b
     T Mi[NOUT + 1], Ui[NOUT + 1];
     constexpr bool RES64 = sizeof(T) == 4;
     Resonance64 res{};
@@ -258,7 +277,7 @@ struct WHelF {
       pt[j] = lc.pt;
       pt2[j] = lc.pt2;
       eta[j] = lc.eta;
-      pass = pass & (lc.pt2 > ptmin2) & (fabs(lc.eta + yb) < (j < NG ? eta_g : eta_mu));
+      pass = pass & (lc.pt2 > ptmin2) & (fabs(fma(T(0.5), dl, lc.eta)) < (j < NG ? eta_g : eta_mu));
     }
     if constexpr (NG == 2) {
       // min(pT_i, pT_j)^2 (Delta eta^2 + Delta phi^2) > pTij^2: with
@@ -277,12 +296,8 @@ struct WHelF {
       pass = pass & ((z <= T(0)) | ((z < T(9.869604401089358)) & (dot < cz * pt[0] * pt[1])));
     }
     if (!pass) return false;
-    T spow = T(1);
-#pragma unroll
-    for (int i = 0; i < NG; ++i) spow *= shat;  // s^(n-3) from V_n / (2 s), s from |A|^2
-    st.Eh = T(0.5) * rs;
     if constexpr (sizeof(T) == 8) st.dm = fma(Mi[NOUT - 1], Mi[NOUT - 1], -Mv2);
-    st.pref = (pre * spow) * (LL * x[0] * vrcp(h));
+    st.x0 = x[0];
     st.la = la;
     st.lb = lb;
     // the gluon helicity configuration, floor(x 2^NG)
@@ -295,7 +310,13 @@ struct WHelF {
   __device__ __forceinline__ T stage2(const State& st, T (&g)[NGRAD + 1]) const {
     const auto& p = st.p;
     const int hel = static_cast<int>(st.hel);
-    const T Eh = st.Eh;
+    const T h = vexp2_fast((st.la + st.lb) * T(0.5 * 1.4426950408889634));  // sqrt(tau), as in stage 1
+    const T rs = sqrtS * h;
+    const T shat = rs * rs;
+    T spow = T(1);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) spow *= shat;  // s^(n-3) from V_n / (2 s), s from |A|^2
+    const T pref = (pre * spow) * (LL * st.x0 * vrcp(h));
 
     // ---- lepton current L = u_L(nu)^dagger sigmabar v_L(mu), sigmabar = (1, -sigma),
     // as its block: L0 + L3 = 2 a1* b1, L0 - L3 = 2 a0* b0, L1 - i L2 = -2 a1* b0,
@@ -328,7 +349,7 @@ struct WHelF {
         const Eps e = eps_out(p[0], ptg, (hel & 1) ? T(1) : T(-1));
         const LC<T> Pk = {q.p, -k.m, -k.x, -k.y};  // p_u - k
         const LC<T> Pq = {k.p, -q.m, k.x, k.y};    // p_u - q
-        const Cx<T> A = sbar_top(Lc, prop(Pk, sbar_u(e.b))) + sbar_top(e.b, prop(Pq, uL));
+        const Cx<T> A = sbar_top_add(Lc, prop(Pk, sbar_u(e.b)), sbar_top(e.b, prop(Pq, uL)));
         cs = T(4) * norm2(A);
       } else {
         const T(&k1)[4] = p[0];
@@ -347,17 +368,17 @@ struct WHelF {
         Cx<T> e12 = {T(0), T(0)}, k2e1 = {T(0), T(0)}, k1e2 = {T(0), T(0)};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          e12 = e12 - e1.v[c] * e2.v[c];
-          k2e1 = k2e1 - k2[c + 1] * e1.v[c];
-          k1e2 = k1e2 - k1[c + 1] * e2.v[c];
+          e12 = cfma(Cx<T>{-e1.v[c].r, -e1.v[c].i}, e2.v[c], e12);
+          k2e1 = cfma(-k2[c + 1], e1.v[c], k2e1);
+          k1e2 = cfma(-k1[c + 1], e2.v[c], k1e2);
         }
         const Cx<T> t2 = T(-2) * iK2 * k2e1, t1 = T(2) * iK2 * k1e2, tk = iK2 * e12;
         const LC<T> dk = {c2.p - c1.p, c2.m - c1.m, c2.x - c1.x, c2.y - c1.y};  // k2 - k1
         SB<T> J;
-        J.p = dk.p * tk + t2 * e2.b.p + t1 * e1.b.p;
-        J.m = dk.m * tk + t2 * e2.b.m + t1 * e1.b.m;
-        J.lo = Cx<T>{dk.x, -dk.y} * tk + t2 * e2.b.lo + t1 * e1.b.lo;
-        J.hi = Cx<T>{dk.x, dk.y} * tk + t2 * e2.b.hi + t1 * e1.b.hi;
+        J.p = cfma(t1, e1.b.p, cfma(t2, e2.b.p, dk.p * tk));
+        J.m = cfma(t1, e1.b.m, cfma(t2, e2.b.m, dk.m * tk));
+        J.lo = cfma(t1, e1.b.lo, cfma(t2, e2.b.lo, Cx<T>{dk.x, -dk.y} * tk));
+        J.hi = cfma(t1, e1.b.hi, cfma(t2, e2.b.hi, Cx<T>{dk.x, dk.y} * tk));
         const LC<T> Pk1 = {c2.p + q.p, -c1.m, -c1.x, -c1.y};                // p_u - k1
         const LC<T> Pk2 = {c1.p + q.p, -c2.m, -c2.x, -c2.y};                // p_u - k2
         const LC<T> PK = {q.p, -(c1.m + c2.m), -(c1.x + c2.x), -(c1.y + c2.y)};  // p_u - k1 - k2
@@ -373,10 +394,11 @@ struct WHelF {
         // (both are linear maps of the spinor they act on).
         const Sp<T> uJ = sbar_u(J);
         const Cx<T> tJ = sbar_top(J, yc);
-        const Cx<T> A12 = sbar_top(Lc, prop(PK, sbar(e1.b, ya) + uJ)) +
-                          sbar_top(e1.b, prop(Pk2q, sbar(Lc, ya) + sbar(e2.b, yc))) + tJ;
-        const Cx<T> A21 = sbar_top(Lc, prop(PK, sbar(e2.b, yw) - uJ)) +
-                          sbar_top(e2.b, prop(Pk1q, sbar(Lc, yw) + sbar(e1.b, yc))) - tJ;
+        const Cx<T> A12 = sbar_top_add(Lc, prop(PK, sbar_add(e1.b, ya, uJ)),
+                                       sbar_top_add(e1.b, prop(Pk2q, sbar_add(Lc, ya, sbar(e2.b, yc))), tJ));
+        const Sp<T> muJ = {{-uJ.a.r, -uJ.a.i}, {-uJ.b.r, -uJ.b.i}};
+        const Cx<T> A21 = sbar_top_add(Lc, prop(PK, sbar_add(e2.b, yw, muJ)),
+                                       sbar_top_add(e2.b, prop(Pk1q, sbar_add(Lc, yw, sbar(e1.b, yc))), Cx<T>{-tJ.r, -tJ.i}));
         cs = T(16.0 / 3.0) * (norm2(A12) + norm2(A21)) - T(4.0 / 3.0) * fma(A12.r, A21.r, A12.i * A21.i);
       }
     }
@@ -384,7 +406,7 @@ struct WHelF {
     const T dm = st.dm;
     const T invD = vrcp(fma(dm, dm, M2G2));
     const T om = vexpm1_fast(st.la) * vexpm1_fast(st.lb);  // (1 - xa)(1 - xb) without cancellation
-    const T f = (st.pref * (om * om * om)) * (cs * invD);
+    const T f = (pref * (om * om * om)) * (cs * invD);
     if (GRAD) {
       g[0] = f * fma(T(4) * M, dm, -twoMG2) * invD;
       g[1] = f * m2M2G * invD;
