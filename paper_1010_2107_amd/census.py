@@ -149,6 +149,8 @@ def whel(n: int) -> Census:
     # (V.sigmabar) x: 28; plus a spinor: 32; its first component: 14, plus a
     # complex number: 16; a propagator (P^2, its reciprocal, P.sigma x): 29
     SBAR, SBAR_ADD, TOP, TOP_ADD, PROP = 28, 32, 14, 16, 29
+    f += 5 * nf  # E = |p| of each final-state momentum (a square root each)
+    t += nf
     f += 2 * 12 + 40  # lepton spinors and current
     t += 2
     if n == 0:

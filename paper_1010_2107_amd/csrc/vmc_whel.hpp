@@ -219,35 +219,35 @@ struct WHelF {
   // from ln xa + ln xb (the same operations as stage 1, bit for bit), the
   // prefactor, |M|^2 and f.
   struct State {
-    T p[NOUT][4];  // g_1..g_NG, mu+, nu in the partonic frame
+    T p[NOUT][3];  // g_1..g_NG, mu+, nu in the partonic frame: momenta (E = |p| is formed in stage 2)
     T x0, dm, hel;  // x0, m_munu^2 - M^2, helicity configuration
     T la, lb;       // ln xa, ln xb: sqrt(s) and the flux factor ((1 - xa)(1 - xb))^3 are formed in stage 2
   };
-  static constexpr int kStateWords = 4 * NOUT + 5;
+  static constexpr int kStateWords = 3 * NOUT + 5;
   static constexpr bool kStaged = sizeof(T) == 4;  // the queue holds FP32
 
   __device__ __forceinline__ static void store_state(const State& st, float* q, int stride, int e) {
 #pragma unroll
     for (int i = 0; i < NOUT; ++i)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) q[(4 * i + c) * stride + e] = static_cast<float>(st.p[i][c]);
-    q[(4 * NOUT + 0) * stride + e] = static_cast<float>(st.x0);
-    q[(4 * NOUT + 1) * stride + e] = static_cast<float>(st.dm);
-    q[(4 * NOUT + 2) * stride + e] = static_cast<float>(st.hel);
-    q[(4 * NOUT + 3) * stride + e] = static_cast<float>(st.la);
-    q[(4 * NOUT + 4) * stride + e] = static_cast<float>(st.lb);
+      for (int c = 0; c < 3; ++c) q[(3 * i + c) * stride + e] = static_cast<float>(st.p[i][c]);
+    q[(3 * NOUT + 0) * stride + e] = static_cast<float>(st.x0);
+    q[(3 * NOUT + 1) * stride + e] = static_cast<float>(st.dm);
+    q[(3 * NOUT + 2) * stride + e] = static_cast<float>(st.hel);
+    q[(3 * NOUT + 3) * stride + e] = static_cast<float>(st.la);
+    q[(3 * NOUT + 4) * stride + e] = static_cast<float>(st.lb);
   }
   __device__ __forceinline__ static State load_state(const float* q, int stride, int e) {
     State st;
 #pragma unroll
     for (int i = 0; i < NOUT; ++i)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) st.p[i][c] = static_cast<T>(q[(4 * i + c) * stride + e]);
-    st.x0 = static_cast<T>(q[(4 * NOUT + 0) * stride + e]);
-    st.dm = static_cast<T>(q[(4 * NOUT + 1) * stride + e]);
-    st.hel = static_cast<T>(q[(4 * NOUT + 2) * stride + e]);
-    st.la = static_cast<T>(q[(4 * NOUT + 3) * stride + e]);
-    st.lb = static_cast<T>(q[(4 * NOUT + 4) * stride + e]);
+      for (int c = 0; c < 3; ++c) st.p[i][c] = static_cast<T>(q[(3 * i + c) * stride + e]);
+    st.x0 = static_cast<T>(q[(3 * NOUT + 0) * stride + e]);
+    st.dm = static_cast<T>(q[(3 * NOUT + 1) * stride + e]);
+    st.hel = static_cast<T>(q[(3 * NOUT + 2) * stride + e]);
+    st.la = static_cast<T>(q[(3 * NOUT + 3) * stride + e]);
+    st.lb = static_cast<T>(q[(3 * NOUT + 4) * stride + e]);
     return st;
   }
 
@@ -264,9 +264,13 @@ struct WHelF {
       res.m2 = shat_fp64(x[0], x[1], L, L_lo, S_hi, S_lo);
       res.Mv2 = static_cast<double>(Mv2) + static_cast<double>(Mv2_lo);
     }
-    rambo_diet<NOUT, 2, RES64>(x, rs, Mi, Ui, st.p, res);
+    T p[NOUT][4];
+    rambo_diet<NOUT, 2, RES64>(x, rs, Mi, Ui, p, res);
     if constexpr (RES64) st.dm = res.dm;
-    const auto& p = st.p;
+#pragma unroll
+    for (int i = 0; i < NOUT; ++i)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) st.p[i][c] = p[i][c + 1];
 
     // ---- cuts: gluons 0..NG-1, the muon NG
     bool pass = true;
@@ -308,7 +312,16 @@ struct WHelF {
 
   template <bool GRAD>
   __device__ __forceinline__ T stage2(const State& st, T (&g)[NGRAD + 1]) const {
-    const auto& p = st.p;
+    // the massless momenta, E = |p| (the same in every kernel, whether the
+    // state came through the queue or not)
+    T p[NOUT][4];
+#pragma unroll
+    for (int i = 0; i < NOUT; ++i) {
+      p[i][1] = st.p[i][0];
+      p[i][2] = st.p[i][1];
+      p[i][3] = st.p[i][2];
+      p[i][0] = vsqrt(fma(p[i][1], p[i][1], fma(p[i][2], p[i][2], p[i][3] * p[i][3])));
+    }
     const int hel = static_cast<int>(st.hel);
     const T h = vexp2_fast((st.la + st.lb) * T(0.5 * 1.4426950408889634));  // sqrt(tau), as in stage 1
     const T rs = sqrtS * h;
