@@ -7,10 +7,9 @@ Checks:
 - Replay: the oracle accumulates the GPU's own FP32 weights (dumped per
   sample) in FP64 (Kawabata's per-cube variance over ng^d cubes), and the
   cube maxima are the maxima of those weights (at least 0).  The dump runs
-  the same stages in another kernel, where the compiler may fuse a
-  different set of multiply-adds: for the one-gluon helicity integrand the
-  dumped weights differ from the accumulated ones by a few ulps (replayed
-  sums 2e-9 apart), for the others not at all (1e-14).  Bounds: S1, S2, I
+  the same stages in another kernel; the library fuses multiply-adds only
+  within one source expression, so both kernels round each weight alike
+  and the replayed sums differ by summation order only.  Bounds: S1, S2, I
   at 1e-7, the variance and the bins at 1e-6, each cube maximum at 1e-6
   relative, the zero-weight count exactly.  A weight added to the wrong
   cube would move that cube's terms by O(1).
