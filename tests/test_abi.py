@@ -96,3 +96,14 @@ def test_integer_arguments_are_range_checked():
         L.call("vmc_workspace_sizes", 4, -2**31 - 1, sizes)
     L.call("vmc_workspace_sizes", 4, 64, sizes)
     assert sizes[0] == 8 * 4 * 65
+
+
+def test_build_flags():
+    """Every unit is built for gfx950 with packed FP32 off and multiply-add
+    fusion only within one source expression (so that every kernel inlining
+    the same integrand code rounds it alike)."""
+    from paper_1010_2107_amd import build as B
+    f = " ".join(B.FLAGS)
+    assert "--offload-arch=gfx950" in f or B.ARCH != "gfx950"
+    assert "-Xclang -target-feature -Xclang -packed-fp32-ops" in f
+    assert "-ffp-contract=on" in B.FLAGS
