@@ -9,14 +9,17 @@ from ._lib import (CONST, DGAUSS, FLAG_FP64, GAUSS, GAUSS_AXES, LINEAR, PSVOL, W
                    VmcNotBuilt, header_functions, lib)
 
 __all__ = ["CONST", "LINEAR", "GAUSS", "DGAUSS", "GAUSS_AXES", "WJETS", "PSVOL", "WHEL", "FLAG_FP64", "VmcError",
-           "VmcNotBuilt", "lib", "header_functions", "Grid", "integrate"]
+           "VmcNotBuilt", "lib", "header_functions", "Grid", "integrate", "GraphedLoop", "Batch", "autotune",
+           "VegasIntegral", "vegas_integral", "Spring"]
+
+# the rest of the surface, imported on first use (torch is loaded then)
+_LAZY = {"Grid": "grid", "integrate": "driver", "GraphedLoop": "driver", "Batch": "batch", "autotune": "autotune",
+         "VegasIntegral": "autograd", "vegas_integral": "autograd", "Spring": "spring"}
 
 
 def __getattr__(name):
-    if name == "Grid":
-        from .grid import Grid
-        return Grid
-    if name == "integrate":
-        from .driver import integrate
-        return integrate
-    raise AttributeError(name)
+    mod = _LAZY.get(name)
+    if mod is None:
+        raise AttributeError(name)
+    import importlib
+    return getattr(importlib.import_module(f".{mod}", __name__), name)
