@@ -156,15 +156,22 @@ constexpr int queue_bytes() {
   return StagedTraits<F>::value ? (kBlock / kWave) * kQueueCap * queue_words<F>() * 4 : 0;
 }
 // The stratified forward kernels queue the owner lane with each entry and
-// keep, per wave, three slots per lane (sum w, sum w^2, largest w of the
-// lane's cube chunk) that other lanes add into.
+// keep, per wave, three slots per cube the wave holds (sum w, sum w^2,
+// largest w of the cube's chunks there) that lanes add the queued weights
+// of other lanes into: 64 / G slots of each kind for G lanes per cube, one
+// when a cube spans whole waves.  The queue's bytes per block (the slots,
+// which depend on G, come on top).
 template <class F>
 constexpr int strat_queue_words() {
   return queue_words<F>() + 1;
 }
 template <class F>
 constexpr int strat_queue_bytes() {
-  return StagedTraits<F>::value ? (kBlock / kWave) * (3 * kWave * 8 + kQueueCap * strat_queue_words<F>() * 4) : 0;
+  return StagedTraits<F>::value ? (kBlock / kWave) * kQueueCap * strat_queue_words<F>() * 4 : 0;
+}
+__host__ __device__ constexpr uint32_t strat_slot_shift(uint32_t log2G) { return log2G < 6 ? log2G : 6; }
+__host__ __device__ constexpr int strat_slot_bytes(uint32_t log2G) {
+  return (kBlock / kWave) * 3 * 8 * (kWave >> strat_slot_shift(log2G));
 }
 
 // LDS layout: grid table first (16-byte entries for FP64), then the histogram
@@ -542,14 +549,19 @@ void k_strat(const SampleArgs A) {
         constexpr int NPK = (D + 3) / 4;
         using State = typename F::State;
         const int lane = threadIdx.x & (kWave - 1);
-        double* slot = hist + 2 * D * A.nbins + (threadIdx.x / kWave) * 3 * kWave;  // [3][64]
-        float* q = reinterpret_cast<float*>(hist + 2 * D * A.nbins + (kBlock / kWave) * 3 * kWave) +
+        // the wave's cubes: lane >> sh (sh = log2 G up to 6), S of them
+        const uint32_t sh = strat_slot_shift(A.log2G);
+        const int S = kWave >> sh;
+        double* slot = hist + 2 * D * A.nbins + (threadIdx.x / kWave) * 3 * S;  // [3][S]
+        float* q = reinterpret_cast<float*>(hist + 2 * D * A.nbins + (kBlock / kWave) * 3 * S) +
                    (threadIdx.x / kWave) * NQ * kQueueCap;
         uint32_t* qj = reinterpret_cast<uint32_t*>(q + (NS + 1) * kQueueCap);
         uint32_t* qo = qj + NPK * kQueueCap;  // owner lane
-        slot[lane] = 0.0;
-        slot[kWave + lane] = 0.0;
-        slot[2 * kWave + lane] = 0.0;
+        if (lane < S) {
+          slot[lane] = 0.0;
+          slot[S + lane] = 0.0;
+          slot[2 * S + lane] = 0.0;
+        }
         __builtin_amdgcn_wave_barrier();
         auto push = [&](int e, const State& st, T jc, const uint32_t (&pk)[NPK]) {
           F::store_state(st, q, kQueueCap, e);
@@ -578,9 +590,10 @@ void k_strat(const SampleArgs A) {
             c2 += wd * wd;
             if (CMAX) cm = fmax(cm, wd);  // a NaN weight never becomes the maximum
           } else {
-            lds_add(&slot[owner], wd);
-            lds_add(&slot[kWave + owner], wd * wd);
-            if (CMAX && wd > 0.0) lds_max_pos(&slot[2 * kWave + owner], wd);
+            const int oc = owner >> sh;  // the owner's cube in the wave
+            lds_add(&slot[oc], wd);
+            lds_add(&slot[S + oc], wd * wd);
+            if (CMAX && wd > 0.0) lds_max_pos(&slot[2 * S + oc], wd);
           }
         };
         const uint32_t nt = static_cast<uint32_t>((static_cast<uint64_t>(A.k) + G - 1) >> A.log2G);
@@ -626,9 +639,12 @@ void k_strat(const SampleArgs A) {
           run(st, jc, pk, owner);
         }
         __builtin_amdgcn_wave_barrier();
-        c1 += slot[lane];
-        c2 += slot[kWave + lane];
-        if (CMAX) cm = fmax(cm, slot[2 * kWave + lane]);
+        if ((lane & ((1 << sh) - 1)) == 0) {  // the first lane of each cube in the wave
+          const int oc = lane >> sh;
+          c1 += slot[oc];
+          c2 += slot[S + oc];
+          if (CMAX) cm = fmax(cm, slot[2 * S + oc]);
+        }
         __builtin_amdgcn_wave_barrier();
       } else {
         for (uint32_t t = t0; t < t1; ++t) {

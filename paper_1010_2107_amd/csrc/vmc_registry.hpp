@@ -17,7 +17,7 @@ struct KernelSet {
   const void* dump_grad;  // the dump with per-sample gradients (NULL without parameters)
   const void* spring;
   int queue_bytes;        // LDS of the plain kernels' stage-2 queue (0: unstaged)
-  int strat_queue_bytes;  // LDS of the stratified forward kernels' queue and slots (0: unstaged)
+  int strat_queue_bytes;  // LDS of the stratified forward kernels' queue (0: unstaged); their slots come on top
   int ngrad;
   int ntheta;
   int tab_entry_bytes;
