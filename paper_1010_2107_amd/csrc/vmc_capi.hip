@@ -365,8 +365,9 @@ int launch_sample(vmc_grid_t g, Plan& P, int kind, hipStream_t stream, bool stat
   if (kind & KIND_FWD) lds += sizeof(double) * 2 * static_cast<size_t>(P.d) * P.A.nbins;
   if (!P.strat) {
     lds += static_cast<size_t>(P.ks->queue_bytes);
-  } else if (!(kind & KIND_ADJ) && P.ks->strat_queue_bytes) {
-    lds += static_cast<size_t>(P.ks->strat_queue_bytes) + static_cast<size_t>(strat_slot_bytes(P.A.log2G));
+  } else if (P.ks->strat_queue_bytes) {
+    const int ng = (kind & KIND_ADJ) ? P.ks->ngrad : 0;
+    lds += static_cast<size_t>(P.ks->strat_queue_bytes) + static_cast<size_t>(strat_slot_bytes(P.A.log2G, ng));
   }
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));

@@ -155,12 +155,13 @@ template <class F>
 constexpr int queue_bytes() {
   return StagedTraits<F>::value ? (kBlock / kWave) * kQueueCap * queue_words<F>() * 4 : 0;
 }
-// The stratified forward kernels queue the owner lane with each entry and
-// keep, per wave, three slots per cube the wave holds (sum w, sum w^2,
-// largest w of the cube's chunks there) that lanes add the queued weights
-// of other lanes into: 64 / G slots of each kind for G lanes per cube, one
-// when a cube spans whole waves.  The queue's bytes per block (the slots,
-// which depend on G, come on top).
+// The stratified kernels of the queued integrands queue the owner lane with
+// each entry and keep, per wave, slots per cube the wave holds (sum w, sum
+// w^2, largest w of the cube's chunks there, then sum and sum of squares of
+// J df/dtheta_q per gradient) that lanes add the queued samples of other
+// lanes into: 64 / G slots of each kind for G lanes per cube, one when a
+// cube spans whole waves.  The queue's bytes per block (the slots, which
+// depend on G and on the gradients, come on top).
 template <class F>
 constexpr int strat_queue_words() {
   return queue_words<F>() + 1;
@@ -170,8 +171,9 @@ constexpr int strat_queue_bytes() {
   return StagedTraits<F>::value ? (kBlock / kWave) * kQueueCap * strat_queue_words<F>() * 4 : 0;
 }
 __host__ __device__ constexpr uint32_t strat_slot_shift(uint32_t log2G) { return log2G < 6 ? log2G : 6; }
-__host__ __device__ constexpr int strat_slot_bytes(uint32_t log2G) {
-  return (kBlock / kWave) * 3 * 8 * (kWave >> strat_slot_shift(log2G));
+__host__ __device__ constexpr int strat_slot_kinds(int ngrad) { return 3 + 2 * ngrad; }
+__host__ __device__ constexpr int strat_slot_bytes(uint32_t log2G, int ngrad) {
+  return (kBlock / kWave) * strat_slot_kinds(ngrad) * 8 * (kWave >> strat_slot_shift(log2G));
 }
 
 // LDS layout: grid table first (16-byte entries for FP64), then the histogram
@@ -541,10 +543,11 @@ void k_strat(const SampleArgs A) {
       double cg1[NG + 1], cg2[NG + 1];
 #pragma unroll
       for (int q = 0; q < NG; ++q) cg1[q] = cg2[q] = 0.0;
-      if constexpr (StagedTraits<F>::value && !GRAD) {
+      if constexpr (StagedTraits<F>::value) {
         // Stage 1 for every sample of the chunk (the loop runs to the
         // longest chunk of the wave), stage 2 on full waves of queued samples.
         constexpr int NQ = strat_queue_words<F>();
+        constexpr int NSL = strat_slot_kinds(NG);
         constexpr int NS = StagedTraits<F>::words;
         constexpr int NPK = (D + 3) / 4;
         using State = typename F::State;
@@ -552,15 +555,16 @@ void k_strat(const SampleArgs A) {
         // the wave's cubes: lane >> sh (sh = log2 G up to 6), S of them
         const uint32_t sh = strat_slot_shift(A.log2G);
         const int S = kWave >> sh;
-        double* slot = hist + 2 * D * A.nbins + (threadIdx.x / kWave) * 3 * S;  // [3][S]
-        float* q = reinterpret_cast<float*>(hist + 2 * D * A.nbins + (kBlock / kWave) * 3 * S) +
+        // after the histogram (forward passes) or right after the table
+        double* const after = hist + (FWD ? 2 * D * A.nbins : 0);
+        double* slot = after + (threadIdx.x / kWave) * NSL * S;  // [NSL][S]
+        float* q = reinterpret_cast<float*>(after + (kBlock / kWave) * NSL * S) +
                    (threadIdx.x / kWave) * NQ * kQueueCap;
         uint32_t* qj = reinterpret_cast<uint32_t*>(q + (NS + 1) * kQueueCap);
         uint32_t* qo = qj + NPK * kQueueCap;  // owner lane
         if (lane < S) {
-          slot[lane] = 0.0;
-          slot[S + lane] = 0.0;
-          slot[2 * S + lane] = 0.0;
+#pragma unroll
+          for (int v = 0; v < NSL; ++v) slot[v * S + lane] = 0.0;
         }
         __builtin_amdgcn_wave_barrier();
         auto push = [&](int e, const State& st, T jc, const uint32_t (&pk)[NPK]) {
@@ -582,18 +586,35 @@ void k_strat(const SampleArgs A) {
 #pragma unroll
           for (int a = 0; a < D; ++a) j[a] = static_cast<int>((pk[a / 4] >> (8 * (a % 4))) & 0xFFu);
           T g[F::NGRAD + 1];
-          const T fv = fn.template stage2<false>(st, g);
+          const T fv = fn.template stage2<GRAD>(st, g);
           accumulate<F, KIND>(A, hist, j, fv, jc, g, acc, cnt);
           const double wd = static_cast<double>(fv * jc);
+          double gd[NG + 1];
+#pragma unroll
+          for (int v = 0; v < NG; ++v) gd[v] = static_cast<double>(g[v] * jc);
           if (owner == lane) {
-            c1 += wd;
-            c2 += wd * wd;
-            if (CMAX) cm = fmax(cm, wd);  // a NaN weight never becomes the maximum
+            if (FWD) {
+              c1 += wd;
+              c2 += wd * wd;
+              if (CMAX) cm = fmax(cm, wd);  // a NaN weight never becomes the maximum
+            }
+#pragma unroll
+            for (int v = 0; v < NG; ++v) {
+              cg1[v] += gd[v];
+              cg2[v] += gd[v] * gd[v];
+            }
           } else {
             const int oc = owner >> sh;  // the owner's cube in the wave
-            lds_add(&slot[oc], wd);
-            lds_add(&slot[S + oc], wd * wd);
-            if (CMAX && wd > 0.0) lds_max_pos(&slot[2 * S + oc], wd);
+            if (FWD) {
+              lds_add(&slot[oc], wd);
+              lds_add(&slot[S + oc], wd * wd);
+              if (CMAX && wd > 0.0) lds_max_pos(&slot[2 * S + oc], wd);
+            }
+#pragma unroll
+            for (int v = 0; v < NG; ++v) {
+              lds_add(&slot[(3 + 2 * v) * S + oc], gd[v]);
+              lds_add(&slot[(4 + 2 * v) * S + oc], gd[v] * gd[v]);
+            }
           }
         };
         const uint32_t nt = static_cast<uint32_t>((static_cast<uint64_t>(A.k) + G - 1) >> A.log2G);
@@ -641,9 +662,16 @@ void k_strat(const SampleArgs A) {
         __builtin_amdgcn_wave_barrier();
         if ((lane & ((1 << sh) - 1)) == 0) {  // the first lane of each cube in the wave
           const int oc = lane >> sh;
-          c1 += slot[oc];
-          c2 += slot[S + oc];
-          if (CMAX) cm = fmax(cm, slot[2 * S + oc]);
+          if (FWD) {
+            c1 += slot[oc];
+            c2 += slot[S + oc];
+            if (CMAX) cm = fmax(cm, slot[2 * S + oc]);
+          }
+#pragma unroll
+          for (int v = 0; v < NG; ++v) {
+            cg1[v] += slot[(3 + 2 * v) * S + oc];
+            cg2[v] += slot[(4 + 2 * v) * S + oc];
+          }
         }
         __builtin_amdgcn_wave_barrier();
       } else {
