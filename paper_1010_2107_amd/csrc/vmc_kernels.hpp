@@ -462,14 +462,14 @@ void k_plain(const SampleArgs A) {
 // between them.  After the cube's samples the chunk sums are combined with
 // lane shuffles (and through LDS across waves) and the first lane adds the
 // cube's k S2_c - S1_c^2 (and its gradient analogue) to the variance sums.
-// Forward passes of integrands that split at the cuts queue the samples that
-// pass, as the plain kernel does; a queued sample's weight returns to the
-// chunk it belongs to through that lane's LDS slots.
+// The passes of integrands that split at the cuts queue the samples that
+// pass, as the plain kernel does; a queued sample's weight (and gradient)
+// returns to the cube it belongs to through the wave's LDS slots.
 // ---------------------------------------------------------------------------
 // The queued forward and fused passes ask for at least 3 waves per SIMD,
-// the occupancy of the plain kernel, which bounds their registers at 168
-// (the fused W + 4 partons pass then spills 32 bytes per lane and still
-// runs 7 % faster than at 2 waves with 186 registers).
+// the occupancy of the plain kernel, which bounds their registers at 168:
+// the fused W + 4 partons pass then spills 108 bytes per lane and runs
+// 1.5 % slower than at 2 waves, the fused W + 2 partons pass 17 % faster.
 template <class F, int KIND>
 constexpr int strat_min_waves() {
   return (StagedTraits<F>::value && (KIND & KIND_FWD)) ? 3 : 1;
