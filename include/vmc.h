@@ -267,7 +267,8 @@ int vmc_dump_samples(vmc_grid_t g, int integrand, const double *theta, int nthet
  * helicity integrands at least two tiles per block the device holds at
  * once unless that takes tiles below 1024 samples; stratified: 256 units, one
  * per thread, or up to 1024 when a unit holds few samples, toward 4096
- * samples per tile, but at least about 512 tiles);
+ * samples per tile (8192 for the W + partons and helicity integrands), but
+ * at least about 512 tiles);
  * chunks_per_cube: lanes that share one cube in stratified mode, a power of
  * two in [1, 256] (up to 64 share a wave, more span the waves of a block),
  * or 0 for the built-in choice (the smallest power of two with ng^dim x

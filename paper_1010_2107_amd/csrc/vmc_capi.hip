@@ -380,13 +380,15 @@ int launch_sample(vmc_grid_t g, Plan& P, int kind, hipStream_t stream, bool stat
     // 8192 samples per block (short blocks even out the cut-dependent cost
     // and the tail of the last wave); stratified: one cube unit per lane,
     // or two or four when units are short, toward 4096 samples per block
-    // (the table load and the bin flush are per block), but at least about
-    // 512 blocks
+    // (8192 for the queued integrands, whose waves drain their queue at
+    // every unit's end; the table load and the bin flush are per block),
+    // but at least about 512 blocks
     uint64_t b = (P.items + 1023) / 1024;
     if (P.strat) {
       const double per_unit = static_cast<double>(A.k) / static_cast<double>(1u << A.log2G);
+      const double toward = P.ks->strat_queue_bytes ? 8192.0 : 4096.0;
       uint64_t r = 1;
-      while (r < 4 && 2.0 * static_cast<double>(r * kBlock) * per_unit <= 4096.0) r <<= 1;
+      while (r < 4 && 2.0 * static_cast<double>(r * kBlock) * per_unit <= toward) r <<= 1;
       b = std::min<uint64_t>(r * kBlock, (P.items + 511) / 512);
     }
     b = ((b + kBlock - 1) / kBlock) * kBlock;
